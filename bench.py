@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the radix-tree-forest sampling path on one MI355X.
+
+One step = the whole hot path over one batch held in HBM:
+    quantise f32 weights -> build guide table + radix tree forest -> sample
+    2^26 uniforms to indices and continuous positions x.
+Workload H24: n = 2^24 uniform(0,1] weights, m = n guide cells, S = 2^26.
+
+Prints one JSON line (the last line of stdout).  ``value`` is samples per
+second of the whole step; build Melem/s, sampling-only samples/s and the two
+same-GPU baselines (binary search, Cutpoint + bisection) are extra fields.
+Kernel times come from HIP events on the stream the library launches on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("samples/s + build Melem/s at n=2^24 (% HBM peak) vs binary search, bit-exact")
+HBM_PEAK_GBS = 8000.0
+NODE_B, TABLE_B, U_B, IDX_B, X_B, W_B = 16, 4, 8, 4, 8, 4
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--log2n", type=int, default=24)
+    p.add_argument("--log2s", type=int, default=26)
+    p.add_argument("--kind", choices=["uniform", "zipf"], default="uniform")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--profile", action="store_true",
+                   help="few steps, no baselines (for rocprofv3 runs)")
+    return p.parse_args()
+
+
+def mean_nodes_visited(key, child, table, m, u):
+    """Mean number of node records Alg. 2 reads per sample (host replay of the
+    descent on the exported forest for a subsample of the uniforms)."""
+    g = ((u.astype(object) * m) >> 64).astype(np.int64)
+    j = table[g].astype(np.int64)
+    visits = np.zeros(u.size, np.int64)
+    active = j >= 0
+    while active.any():
+        ja = j[active]
+        visits[active] += 1
+        go_left = u[active] < key[ja]
+        j[active] = np.where(go_left, child[ja, 0], child[ja, 1])
+        active = j >= 0
+    return float(visits.mean())
+
+
+def timed(fn, start, stop, reps):
+    ts = []
+    for _ in range(reps):
+        start.record()
+        fn()
+        stop.record()
+        stop.synchronize()
+        ts.append(start.elapsed_time(stop))
+    return float(np.mean(ts)), ts
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the forest of "
+              "one distribution is built and sampled on a single device", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1901_05423_amd as rtf
+    from paper_1901_05423_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    n, S = 1 << args.log2n, 1 << args.log2s
+    m = n
+    cid = wl.H24_UNIFORM if args.kind == "uniform" else wl.H24_ZIPF
+    r = wl.rng(cid)
+    v_h = wl.weights_uniform(r, n) if args.kind == "uniform" else wl.weights_zipf(r, n)
+    u_h = wl.uniforms(r, S)
+    v = torch.from_numpy(v_h).to(dev)
+    u = torch.from_numpy(u_h).to(dev)
+    q = torch.empty(n, dtype=torch.uint32, device=dev)
+    scale = torch.empty(1, dtype=torch.float64, device=dev)
+    idx = torch.empty(S, dtype=torch.int32, device=dev)
+    x = torch.empty(S, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    holder = {}
+
+    ws = torch.empty(rtf.lib().rtf_workspace_bytes(n, m), dtype=torch.uint8, device=dev)
+
+    def step():
+        rtf.quantize(v, out=(q, scale))
+        holder["f"] = rtf.build(q, m, ws=ws)
+        rtf.sample(holder["f"], u, out=(idx, x))
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    # warmup
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    holder["f"].check()
+
+    # timed whole steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for _ in range(args.steps):
+        step()
+    ev[1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev[0].elapsed_time(ev[1]) / args.steps
+
+    # per-phase times (each its own launch sequence, events on the same stream)
+    f = holder["f"]
+    reps = max(3, args.steps)
+    t_quant, _ = timed(lambda: rtf.quantize(v, out=(q, scale)), ev[2], ev[3], reps)
+    t_build, _ = timed(lambda: rtf.build(q, m, ws=ws), ev[2], ev[3], reps)
+    t_sample, _ = timed(lambda: rtf.sample(f, u, out=(idx, x)), ev[2], ev[3], reps)
+    out = {}
+    if not args.profile:
+        t_bs, _ = timed(lambda: rtf.sample_bsearch(f, u, out=(idx, x)), ev[2], ev[3], reps)
+        t_cb, _ = timed(lambda: rtf.sample_cutpoint_bsearch(f, u, out=(idx, x)), ev[2], ev[3],
+                        reps)
+        rtf.sample(f, u, out=(idx, x))
+        out["bsearch_samples_s"] = S / (t_bs * 1e-3)
+        out["cutpoint_bsearch_samples_s"] = S / (t_cb * 1e-3)
+    torch.cuda.synchronize()
+
+    # algorithmic bytes per sample of the sampling kernel: stream u, idx, x;
+    # one guide entry; the node records the descent reads; the two keys the
+    # position reads (one record pair)
+    key, child, table, W = f.export()
+    sub = u_h[:: max(1, S // (1 << 20))]
+    dbar = mean_nodes_visited(key, child, table, m, sub)
+    per_sample = U_B + IDX_B + X_B + TABLE_B + NODE_B * dbar + 2 * NODE_B
+    sample_bytes = per_sample * S
+    build_bytes = (W_B + NODE_B) * n + TABLE_B * m
+    achieved = sample_bytes / (t_sample * 1e-3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": S / (ms_step * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"H24-{args.kind}: one distribution of n=2^{args.log2n} "
+                        f"{'uniform(0,1]' if args.kind == 'uniform' else 'Zipf(1.1) permuted'} "
+                        f"f32 weights quantised to u32, m=n guide cells, S=2^{args.log2s} u64 "
+                        "uniforms -> int32 index + f64 position",
+            "n": n, "m": m, "samples": S,
+        },
+        "phase_ms": {"quantize": t_quant, "build": t_build, "sample": t_sample},
+        "build_melem_s": n / (t_build * 1e-3) / 1e6,
+        "build_hbm_frac": build_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "sample_only_samples_s": S / (t_sample * 1e-3),
+        "mean_nodes_per_sample": dbar,
+        "roofline": {
+            "kernel": "k_sample (Alg. 2 descent + position)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_sample": per_sample,
+        },
+        "wall_s_timed": wall,
+    }
+    result.update(out)
+
+    if not args.no_cpu and not args.profile:
+        result["cpu_baseline"] = cpu_baseline(v_h, u_h, n, m)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(v_h, u_h, n, m):
+    """The CPU oracle as it stands (single thread): quantise, prefix sum and
+    binary search with x on a bounded subsample of the uniforms."""
+    import oracle
+    t0 = time.perf_counter()
+    q, _ = oracle.quantize(v_h)
+    C = oracle.prefix(q)
+    t_setup = time.perf_counter() - t0
+    k = 1 << 22
+    us = u_h[:k]
+    t0 = time.perf_counter()
+    oracle.search(q, us, C=C)
+    t_search = time.perf_counter() - t0
+    S = u_h.size
+    total = t_setup + t_search * (S / k)
+    t0 = time.perf_counter()
+    oracle.forest(q, m=m)
+    t_forest = time.perf_counter() - t0
+    return {
+        "value": S / total,
+        "unit": "samples/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"quantise + prefix over all n=2^{int(np.log2(n))} weights "
+                  f"({t_setup:.2f} s) plus binary search with x on the first 2^22 of the "
+                  f"2^{int(np.log2(S))} uniforms ({t_search:.2f} s), scaled to the full step",
+        "oracle_forest_melem_s": n / t_forest / 1e6,
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,238 @@
+/*
+ * rtforest.h -- C ABI of the MI355X (gfx950) radix-tree-forest sampler.
+ *
+ * Method: Binder & Keller, "Massively Parallel Construction of Radix Tree
+ * Forests for the Efficient Sampling of Discrete or Piecewise Constant
+ * Probability Distributions" (arXiv:1901.05423).
+ *
+ * Problem (Sec. 1): given weights w_0..w_{n-1} >= 0 with positive sum, map a
+ * uniform xi in [0,1) to the index i with P_i <= xi < P_{i+1}, where P_k is
+ * the normalised partial sum of the first k weights.  The library builds the
+ * auxiliary structure of Sec. 3 -- a guide table of m equal cells (Sec. 2.5)
+ * plus one radix tree per cell (the radix tree forest, Sec. 3.2, Alg. 1) --
+ * and evaluates Alg. 2 for batches of samples.
+ *
+ * Number formats.  Weights are uint32.  Partial sums C_i are exact uint64.  A
+ * uniform is a uint64 u standing for xi = u * 2^-64.  Interval i's lower bound
+ * is stored as the 0.64 fixed-point key U_i = ceil(C_i * 2^64 / W), W = C_n;
+ * then U_i <= u exactly when C_i <= floor(u*W / 2^64), so the sampled index
+ * equals the exact real-number inverse CDF, bit for bit.  Indices are 0-based
+ * int32.  The continuous position x (Sec. 5) is FP64 in [0,1]:
+ *     x = (i + ((t - C_i) + lo * 2^-64) / w_i) / n,   t:lo = u * W (128 bit).
+ *
+ * Conventions.
+ *  - Every array argument is a DEVICE pointer owned by the caller unless its
+ *    name starts with h_ (host pointer).  The library never allocates device
+ *    memory and never frees any.
+ *  - All calls are asynchronous on the given stream and return once the work
+ *    is enqueued, except rtf_check and rtf_forest_export, which synchronise
+ *    the stream.
+ *  - Errors are returned as rtf_status; nothing is thrown across the ABI.
+ *    Argument errors are detected on the host before anything is enqueued.
+ *    Errors in the data (a distribution whose weights are all zero, a negative
+ *    or non-finite weight) are detected on the device, recorded in the
+ *    forest's status word and reported by rtf_check.
+ *  - Pointers to 64-bit element arrays must be 8-byte aligned, to 32-bit
+ *    element arrays 4-byte aligned; workspaces 256-byte aligned.
+ */
+#ifndef RTFOREST_H
+#define RTFOREST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rtf_status {
+    RTF_OK = 0,
+    RTF_ERR_INVALID_ARG = 1, /* null or misaligned pointer, n < 1, m < 1, D < 1 */
+    RTF_ERR_SIZE = 2,        /* a size beyond 2^31 - 1 (int32 leaf references) */
+    RTF_ERR_WORKSPACE = 3,   /* workspace smaller than the *_workspace_bytes call */
+    RTF_ERR_HIP = 4,         /* a HIP launch or runtime error */
+    RTF_ERR_ZERO_TOTAL = 5,  /* a distribution whose weights sum to zero */
+    RTF_ERR_VALUE = 6        /* rtf_quantize_f32: negative, NaN or infinite weight */
+} rtf_status;
+
+/*
+ * Descriptor of a built forest.  Plain data: it holds pointers into the
+ * caller's workspace and is valid while that workspace lives and is not used
+ * for another build.  The node array holds n_total 16-byte records
+ * { uint64 key U_j; int32 child[2]; } where node j splits between leaf j-1 and
+ * leaf j and compares against U_j (Sec. 3.1).  A reference r >= 0 is a node, a
+ * reference r < 0 is leaf ~r.  table[g] is a node (the first node of cell g,
+ * whose child 1 roots the cell's tree and whose child 0 is the interval
+ * overlapping the cell from the left) or, for a cell that no lower bound falls
+ * in, the complement of the one leaf covering it (Sec. 3.2).
+ */
+typedef struct rtf_forest {
+    int32_t D;          /* number of distributions */
+    int32_t tile;       /* elements per build tile */
+    int64_t n_total;    /* leaves = nodes over all distributions */
+    int64_t m_total;    /* guide cells over all distributions */
+    void *nodes;        /* device: n_total node records */
+    int32_t *table;     /* device: m_total guide entries */
+    void *dists;        /* device: D per-distribution parameter records */
+    int64_t *elem_off;  /* device: D+1 element offsets (copied at build) */
+    int64_t *cell_off;  /* device: D+1 cell offsets (copied at build) */
+    uint32_t *status;   /* device: status word (bit set per rtf_status code) */
+    void *scratch;      /* device: build scratch */
+    size_t scratch_bytes;
+} rtf_forest;
+
+/* ---- workspace sizing ------------------------------------------------- */
+
+/* Bytes of workspace for rtf_build of one distribution of n weights and m
+ * guide cells; 0 if n or m is out of range. */
+size_t rtf_workspace_bytes(int64_t n, int64_t m);
+
+/* Bytes of workspace for rtf_build_batched of D distributions holding
+ * n_total weights and m_total guide cells in all; 0 if out of range. */
+size_t rtf_workspace_bytes_batched(int32_t D, int64_t n_total, int64_t m_total);
+
+/* ---- construction (Sec. 3.1-3.2, Alg. 1; Sec. 5 for many at once) -------- */
+
+/*
+ * Build the guide table and radix tree forest of one distribution.
+ *   w        uint32[n] weights (zeros allowed; not all zero)
+ *   n        number of weights, 1 <= n <= 2^31 - 1
+ *   m        number of guide cells, 1 <= m <= 2^31 - 1 (Sec. 3: "proportional
+ *            to n" -- m = n is the usual choice)
+ *   ws       workspace of at least rtf_workspace_bytes(n, m) bytes, 256-byte
+ *            aligned; it holds the forest afterwards
+ *   out      host pointer; receives the descriptor
+ * The weights are read during the call's kernels only.  An all-zero w is
+ * reported by rtf_check as RTF_ERR_ZERO_TOTAL; sampling it gives idx -1 and
+ * x NaN.  Bit-exact and deterministic: the forest depends only on (w, m).
+ */
+rtf_status rtf_build(const uint32_t *w, int64_t n, int64_t m, void *ws,
+                     size_t ws_bytes, hipStream_t stream, rtf_forest *out);
+
+/*
+ * Build the forests of D distributions stored back to back in one launch
+ * sequence (Sec. 5: a distribution's index range is one more boundary that
+ * merges never cross).
+ *   w         uint32[n_total] weights, distribution d at [elem_off[d], elem_off[d+1])
+ *   elem_off  int64[D+1] device offsets, elem_off[0] = 0, strictly increasing,
+ *             elem_off[D] = n_total (every distribution has >= 1 weight)
+ *   cell_off  int64[D+1] device offsets of the guide cells, cell_off[0] = 0,
+ *             strictly increasing, cell_off[D] = m_total
+ * Node and leaf references are global (leaf i of distribution d is
+ * elem_off[d] + i); the sampling calls return indices local to d.  Offsets
+ * are copied into the workspace.  Offsets that break the rules above are
+ * undefined behaviour (they are not read back to the host).
+ */
+rtf_status rtf_build_batched(const uint32_t *w, const int64_t *elem_off,
+                             const int64_t *cell_off, int32_t D,
+                             int64_t n_total, int64_t m_total, void *ws,
+                             size_t ws_bytes, hipStream_t stream,
+                             rtf_forest *out);
+
+/* ---- sampling (Alg. 2, Sec. 5) ---------------------------------------- */
+
+/*
+ * Alg. 2 for S uniforms of distribution 0 of f:
+ *   u        uint64[S] uniforms (xi = u * 2^-64)
+ *   out_idx  int32[S]: the i with P_i <= xi < P_{i+1}
+ *   out_x    double[S] continuous position x, or NULL to skip it
+ * S may be 0 (nothing is launched).
+ */
+rtf_status rtf_sample(const rtf_forest *f, const uint64_t *u, int64_t S,
+                      int32_t *out_idx, double *out_x, hipStream_t stream);
+
+/*
+ * Alg. 2 for a batch: samples [sample_off[d], sample_off[d+1]) of u belong to
+ * distribution d (int64[D+1] device offsets, non-decreasing, sample_off[D] = S;
+ * empty ranges allowed).  Indices are local to each distribution.
+ */
+rtf_status rtf_sample_batched(const rtf_forest *f, const int64_t *sample_off,
+                              const uint64_t *u, int64_t S, int32_t *out_idx,
+                              double *out_x, hipStream_t stream);
+
+/*
+ * Two-dimensional inversion (Sec. 5): distribution 0 of f is the marginal
+ * over R rows and distributions 1..R are the rows (so D = R + 1 and the
+ * marginal has R weights).  For pair s, u2[2s] picks the row r from the
+ * marginal and u2[2s+1] the column c from row r.
+ *   out_rc   int32[2S]: (r, c) per pair
+ *   out_xy   double[2S]: (y, x) continuous positions of the row and the
+ *            column, or NULL
+ */
+rtf_status rtf_sample_2d(const rtf_forest *f, const uint64_t *u2, int64_t S,
+                         int32_t *out_rc, double *out_xy, hipStream_t stream);
+
+/* Baseline of the same mapping by plain binary search over the forest's keys
+ * (Sec. 2.2); identical output to rtf_sample (Sec. 4). */
+rtf_status rtf_sample_bsearch(const rtf_forest *f, const uint64_t *u,
+                              int64_t S, int32_t *out_idx, double *out_x,
+                              hipStream_t stream);
+
+/* Baseline of the same mapping by the guide table plus binary search inside
+ * the cell (the Cutpoint Method with bisection, Sec. 2.5); identical output. */
+rtf_status rtf_sample_cutpoint_bsearch(const rtf_forest *f, const uint64_t *u,
+                                       int64_t S, int32_t *out_idx,
+                                       double *out_x, hipStream_t stream);
+
+/* ---- quantisation and differentiation (extensions) ---------------------- */
+
+/*
+ * Quantise non-negative float weights to uint32, per distribution:
+ * s_d = (2^32-1) / max(v over d) in FP64, q = rint(v * s_d) clamped to
+ * [1, 2^32-1] for v > 0, q = 0 for v == 0; scale[d] = s_d (0 if all zero).
+ *   v         float[n_total]; elem_off int64[D+1] device offsets as in
+ *             rtf_build_batched (NULL with D == 1 means [0, n_total])
+ *   out       uint32[n_total]; scale double[D]
+ *   status    uint32 device status word that receives RTF_ERR_VALUE for a
+ *             negative, NaN or infinite weight (may be NULL)
+ */
+rtf_status rtf_quantize_f32(const float *v, const int64_t *elem_off, int32_t D,
+                            int64_t n_total, uint32_t *out, double *scale,
+                            uint32_t *status, hipStream_t stream);
+
+/* Bytes of workspace rtf_backward needs for a forest of D distributions and
+ * n_total weights. */
+size_t rtf_backward_workspace_bytes(int32_t D, int64_t n_total);
+
+/*
+ * Adjoint of x with respect to the real weights v = q / scale (the sampled
+ * index is piecewise constant and held fixed).  For distribution d with n_d
+ * weights and a_s = grad_x[s] / (n_d * w_{i_s}):
+ *   grad_w[k] = sum_s a_s xi_s - sum_{s: i_s > k} a_s - sum_{s: i_s = k} a_s frac_s
+ * over the samples s of d, where frac_s = x_s * n_d - i_s.
+ *   sample_off int64[D+1] as in rtf_sample_batched (NULL with D == 1)
+ *   u, idx     the forward call's uniforms and local indices
+ *   grad_x     double[S]; scale double[D] from rtf_quantize_f32
+ *   grad_w     double[n_total] (written, not accumulated)
+ *   ws         rtf_backward_workspace_bytes(D, n_total) bytes, 256-aligned
+ * Samples with idx < 0 are ignored.
+ */
+rtf_status rtf_backward(const rtf_forest *f, const int64_t *sample_off,
+                        const uint64_t *u, const int32_t *idx,
+                        const double *grad_x, int64_t S, const double *scale,
+                        double *grad_w, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* ---- inspection --------------------------------------------------------- */
+
+/* Synchronise the stream and return the first error recorded in the forest's
+ * status word (RTF_OK if none). */
+rtf_status rtf_check(const rtf_forest *f, hipStream_t stream);
+
+/* Synchronise and copy the forest to host buffers (each may be NULL):
+ * h_nodes receives the n_total 16-byte node records as stored (uint64 key,
+ * int32 child 0, int32 child 1; 16 * n_total bytes), h_table int32[m_total],
+ * h_W uint64[D] the distributions' total weights. */
+rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, int32_t *h_table,
+                             uint64_t *h_W, hipStream_t stream);
+
+/* Static string naming a status code. */
+const char *rtf_status_string(rtf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTFOREST_H */

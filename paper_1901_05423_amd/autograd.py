@@ -1,0 +1,42 @@
+"""Differentiable sampling: x as a function of the real weights.
+
+Forward: quantise the weights (per distribution), build the forest, sample.
+Backward: the library's adjoint kernel gives dL/dv for the continuous position
+x of Sec. 5 with the sampled index held fixed; autograd then chains whatever
+produced v (e.g. a softplus of logits).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import backward, build_batched, cells_like, quantize, sample_batched
+
+
+class RTFSample(torch.autograd.Function):
+    """x = RTFSample.apply(v, u, elem_off, sample_off, cell_ratio)
+
+    v           float32[n_total] non-negative weights (requires_grad allowed)
+    u           uint64[S] uniforms; sample_off int64[D+1] splits them by
+                distribution; elem_off int64[D+1] splits v
+    cell_ratio  guide cells per weight (m_d = round(ratio * n_d), at least 1)
+    Returns x float64[S]; the sampled indices are kept in ``ctx`` and exposed
+    through the ``last_indices`` attribute of the returned tensor.
+    """
+
+    @staticmethod
+    def forward(ctx, v, u, elem_off, sample_off, cell_ratio=1.0):
+        q, scale = quantize(v.detach().contiguous(), elem_off)
+        f = build_batched(q, elem_off, cells_like(elem_off, cell_ratio))
+        idx, x = sample_batched(f, sample_off, u, want_x=True)
+        ctx.forest = f
+        ctx.save_for_backward(u, idx, scale, sample_off)
+        ctx.v_dtype = v.dtype
+        x.last_indices = idx
+        return x
+
+    @staticmethod
+    def backward(ctx, grad_x):
+        u, idx, scale, sample_off = ctx.saved_tensors
+        g = backward(ctx.forest, u, idx, grad_x.contiguous().to(torch.float64), scale,
+                     sample_off=sample_off)
+        return g.to(ctx.v_dtype), None, None, None, None

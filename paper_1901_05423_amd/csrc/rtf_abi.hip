@@ -1,0 +1,287 @@
+// rtf_abi.hip -- the extern "C" entry points of include/rtforest.h: argument
+// checks, workspace layout and kernel launches.  Host code only.
+#include <stdlib.h>
+#include <string.h>
+
+#include "rtf_internal.h"
+
+using namespace rtf;
+
+namespace {
+
+constexpr int64_t MAX_I32 = 2147483647;
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace layout of a forest of D distributions, n_total leaves, m_total cells.
+struct Layout {
+    size_t status, nodes, table, dists, eoff, coff, tsum, tpre, dloc, dcnt, ditems, total;
+    int64_t ntiles;
+};
+
+Layout make_layout(int32_t D, int64_t n, int64_t m) {
+    Layout L;
+    L.ntiles = (n + TILE - 1) / TILE;
+    size_t o = 0;
+    L.status = o;
+    o = align256(o + 256);
+    L.nodes = o;
+    o = align256(o + sizeof(Node) * (size_t)n);
+    L.table = o;
+    o = align256(o + sizeof(int32_t) * (size_t)m);
+    L.dists = o;
+    o = align256(o + sizeof(Dist) * (size_t)D);
+    L.eoff = o;
+    o = align256(o + sizeof(int64_t) * (size_t)(D + 1));
+    L.coff = o;
+    o = align256(o + sizeof(int64_t) * (size_t)(D + 1));
+    L.tsum = o;
+    o = align256(o + sizeof(uint64_t) * (size_t)L.ntiles);
+    L.tpre = o;
+    o = align256(o + sizeof(uint64_t) * (size_t)L.ntiles);
+    L.dloc = o;
+    o = align256(o + sizeof(uint64_t) * (size_t)D);
+    L.dcnt = o;
+    o = align256(o + sizeof(int32_t) * (size_t)L.ntiles);
+    L.ditems = o;
+    o = align256(o + sizeof(int64_t) * (size_t)L.ntiles * DEFER_CAP);
+    L.total = o;
+    return L;
+}
+
+bool sizes_ok(int32_t D, int64_t n, int64_t m) {
+    return D >= 1 && n >= D && m >= D && n <= MAX_I32 && m <= MAX_I32;
+}
+
+template <typename T>
+bool aligned(const T *p, size_t a) {
+    return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0;
+}
+
+rtf_status from_hip(hipError_t e) { return e == hipSuccess ? RTF_OK : RTF_ERR_HIP; }
+
+rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_t *cell_off,
+                        int32_t D, int64_t n, int64_t m, void *ws, size_t ws_bytes,
+                        hipStream_t st, rtf_forest *out) {
+    if (!w || !ws || !out || !aligned(w, 4) || !aligned(ws, 256)) return RTF_ERR_INVALID_ARG;
+    if (D > 1 && (!elem_off || !cell_off || !aligned(elem_off, 8) || !aligned(cell_off, 8)))
+        return RTF_ERR_INVALID_ARG;
+    if (n < 1 || m < 1 || D < 1) return RTF_ERR_INVALID_ARG;
+    if (!sizes_ok(D, n, m)) return RTF_ERR_SIZE;
+    const Layout L = make_layout(D, n, m);
+    if (ws_bytes < L.total) return RTF_ERR_WORKSPACE;
+    char *b = static_cast<char *>(ws);
+    rtf_forest f;
+    memset(&f, 0, sizeof f);
+    f.D = D;
+    f.tile = TILE;
+    f.n_total = n;
+    f.m_total = m;
+    f.nodes = b + L.nodes;
+    f.table = reinterpret_cast<int32_t *>(b + L.table);
+    f.dists = b + L.dists;
+    f.elem_off = reinterpret_cast<int64_t *>(b + L.eoff);
+    f.cell_off = reinterpret_cast<int64_t *>(b + L.coff);
+    f.status = reinterpret_cast<uint32_t *>(b + L.status);
+    f.scratch = b + L.tsum;
+    f.scratch_bytes = L.total - L.tsum;
+
+    hipError_t e = launch_copy_offsets(D > 1 ? elem_off : nullptr, D > 1 ? cell_off : nullptr,
+                                       f.elem_off, f.cell_off, D, n, m, f.status, st);
+    if (e != hipSuccess) return RTF_ERR_HIP;
+    BuildArgs a;
+    a.w = w;
+    a.elem_off = f.elem_off;
+    a.cell_off = f.cell_off;
+    a.D = D;
+    a.n_total = n;
+    a.m_total = m;
+    a.ntiles = L.ntiles;
+    a.nodes = static_cast<Node *>(f.nodes);
+    a.table = f.table;
+    a.dists = static_cast<Dist *>(f.dists);
+    a.status = f.status;
+    a.tile_sum = reinterpret_cast<uint64_t *>(b + L.tsum);
+    a.tile_prefix = reinterpret_cast<uint64_t *>(b + L.tpre);
+    a.dist_local = reinterpret_cast<uint64_t *>(b + L.dloc);
+    a.defer_count = reinterpret_cast<int32_t *>(b + L.dcnt);
+    a.defer_items = reinterpret_cast<int64_t *>(b + L.ditems);
+    e = launch_build(a, st);
+    if (e != hipSuccess) return RTF_ERR_HIP;
+    *out = f;
+    return RTF_OK;
+}
+
+bool forest_ok(const rtf_forest *f) {
+    return f && f->nodes && f->table && f->dists && f->status && f->D >= 1 &&
+           sizes_ok(f->D, f->n_total, f->m_total);
+}
+
+bool sample_args_ok(const uint64_t *u, int64_t S, const int32_t *idx, const double *x) {
+    if (S < 0) return false;
+    if (S == 0) return true;
+    return u && idx && aligned(u, 8) && aligned(idx, 4) && (!x || aligned(x, 8));
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rtf_workspace_bytes(int64_t n, int64_t m) {
+    if (n < 1 || m < 1 || !sizes_ok(1, n, m)) return 0;
+    return make_layout(1, n, m).total;
+}
+
+size_t rtf_workspace_bytes_batched(int32_t D, int64_t n_total, int64_t m_total) {
+    if (!sizes_ok(D, n_total, m_total)) return 0;
+    return make_layout(D, n_total, m_total).total;
+}
+
+rtf_status rtf_build(const uint32_t *w, int64_t n, int64_t m, void *ws, size_t ws_bytes,
+                     hipStream_t stream, rtf_forest *out) {
+    return build_common(w, nullptr, nullptr, 1, n, m, ws, ws_bytes, stream, out);
+}
+
+rtf_status rtf_build_batched(const uint32_t *w, const int64_t *elem_off, const int64_t *cell_off,
+                             int32_t D, int64_t n_total, int64_t m_total, void *ws,
+                             size_t ws_bytes, hipStream_t stream, rtf_forest *out) {
+    if (D < 1 || !elem_off || !cell_off) return RTF_ERR_INVALID_ARG;
+    if (D == 1) {
+        // offsets still copied so that the descriptor is self-contained
+        if (!aligned(elem_off, 8) || !aligned(cell_off, 8)) return RTF_ERR_INVALID_ARG;
+    }
+    return build_common(w, elem_off, cell_off, D, n_total, m_total, ws, ws_bytes, stream, out);
+}
+
+rtf_status rtf_sample(const rtf_forest *f, const uint64_t *u, int64_t S, int32_t *out_idx,
+                      double *out_x, hipStream_t stream) {
+    if (!forest_ok(f) || !sample_args_ok(u, S, out_idx, out_x)) return RTF_ERR_INVALID_ARG;
+    if (S == 0) return RTF_OK;
+    return from_hip(launch_sample(static_cast<const Node *>(f->nodes), f->table,
+                                  static_cast<const Dist *>(f->dists), nullptr, 1, f->n_total, u, S,
+                                  out_idx, out_x, stream));
+}
+
+rtf_status rtf_sample_batched(const rtf_forest *f, const int64_t *sample_off, const uint64_t *u,
+                              int64_t S, int32_t *out_idx, double *out_x, hipStream_t stream) {
+    if (!forest_ok(f) || !sample_args_ok(u, S, out_idx, out_x)) return RTF_ERR_INVALID_ARG;
+    if (!sample_off || !aligned(sample_off, 8)) return RTF_ERR_INVALID_ARG;
+    if (S == 0) return RTF_OK;
+    return from_hip(launch_sample(static_cast<const Node *>(f->nodes), f->table,
+                                  static_cast<const Dist *>(f->dists), sample_off, f->D, f->n_total,
+                                  u, S, out_idx, out_x, stream));
+}
+
+rtf_status rtf_sample_2d(const rtf_forest *f, const uint64_t *u2, int64_t S, int32_t *out_rc,
+                         double *out_xy, hipStream_t stream) {
+    if (!forest_ok(f) || f->D < 2 || !sample_args_ok(u2, S, out_rc, out_xy))
+        return RTF_ERR_INVALID_ARG;
+    if (S == 0) return RTF_OK;
+    return from_hip(launch_sample_2d(static_cast<const Node *>(f->nodes), f->table,
+                                     static_cast<const Dist *>(f->dists), f->D, f->n_total, u2, S,
+                                     out_rc, out_xy, stream));
+}
+
+rtf_status rtf_sample_bsearch(const rtf_forest *f, const uint64_t *u, int64_t S,
+                              int32_t *out_idx, double *out_x, hipStream_t stream) {
+    if (!forest_ok(f) || !sample_args_ok(u, S, out_idx, out_x)) return RTF_ERR_INVALID_ARG;
+    if (S == 0) return RTF_OK;
+    return from_hip(launch_sample_bsearch(static_cast<const Node *>(f->nodes), f->table,
+                                          static_cast<const Dist *>(f->dists), false, u, S,
+                                          out_idx, out_x, stream));
+}
+
+rtf_status rtf_sample_cutpoint_bsearch(const rtf_forest *f, const uint64_t *u, int64_t S,
+                                       int32_t *out_idx, double *out_x, hipStream_t stream) {
+    if (!forest_ok(f) || !sample_args_ok(u, S, out_idx, out_x)) return RTF_ERR_INVALID_ARG;
+    if (S == 0) return RTF_OK;
+    return from_hip(launch_sample_bsearch(static_cast<const Node *>(f->nodes), f->table,
+                                          static_cast<const Dist *>(f->dists), true, u, S,
+                                          out_idx, out_x, stream));
+}
+
+rtf_status rtf_quantize_f32(const float *v, const int64_t *elem_off, int32_t D, int64_t n_total,
+                            uint32_t *out, double *scale, uint32_t *status,
+                            hipStream_t stream) {
+    if (!v || !out || !scale || D < 1 || n_total < 1) return RTF_ERR_INVALID_ARG;
+    if (!aligned(v, 4) || !aligned(out, 4) || !aligned(scale, 8) ||
+        (status && !aligned(status, 4)))
+        return RTF_ERR_INVALID_ARG;
+    if (D > 1 && (!elem_off || !aligned(elem_off, 8))) return RTF_ERR_INVALID_ARG;
+    if (n_total > MAX_I32 || n_total < D) return RTF_ERR_SIZE;
+    return from_hip(
+        launch_quantize(v, D > 1 ? elem_off : nullptr, D, n_total, out, scale, status, stream));
+}
+
+size_t rtf_backward_workspace_bytes(int32_t D, int64_t n_total) {
+    if (D < 1 || n_total < D || n_total > MAX_I32) return 0;
+    return align256(sizeof(double) * (size_t)n_total) * 2 + align256(sizeof(double) * (size_t)D);
+}
+
+rtf_status rtf_backward(const rtf_forest *f, const int64_t *sample_off, const uint64_t *u,
+                        const int32_t *idx, const double *grad_x, int64_t S, const double *scale,
+                        double *grad_w, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (!forest_ok(f) || !scale || !grad_w || !ws || S < 0) return RTF_ERR_INVALID_ARG;
+    if (S > 0 && (!u || !idx || !grad_x)) return RTF_ERR_INVALID_ARG;
+    if (f->D > 1 && !sample_off) return RTF_ERR_INVALID_ARG;
+    if (!aligned(ws, 256) || !aligned(grad_w, 8) || !aligned(scale, 8))
+        return RTF_ERR_INVALID_ARG;
+    if (ws_bytes < rtf_backward_workspace_bytes(f->D, f->n_total)) return RTF_ERR_WORKSPACE;
+    char *b = static_cast<char *>(ws);
+    double *B = reinterpret_cast<double *>(b);
+    double *Dv = reinterpret_cast<double *>(b + align256(sizeof(double) * (size_t)f->n_total));
+    double *A = reinterpret_cast<double *>(b + 2 * align256(sizeof(double) * (size_t)f->n_total));
+    return from_hip(launch_backward(static_cast<const Node *>(f->nodes),
+                                    static_cast<const Dist *>(f->dists), f->D, f->n_total,
+                                    f->D > 1 ? sample_off : nullptr, u, idx, grad_x, S, scale,
+                                    grad_w, B, Dv, A, stream));
+}
+
+rtf_status rtf_check(const rtf_forest *f, hipStream_t stream) {
+    if (!forest_ok(f)) return RTF_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RTF_ERR_HIP;
+    uint32_t s = 0;
+    if (hipMemcpy(&s, f->status, sizeof s, hipMemcpyDeviceToHost) != hipSuccess)
+        return RTF_ERR_HIP;
+    for (int c = 1; c < 32; ++c)
+        if (s & (1u << c)) return static_cast<rtf_status>(c);
+    return RTF_OK;
+}
+
+rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, int32_t *h_table,
+                             uint64_t *h_W, hipStream_t stream) {
+    if (!forest_ok(f)) return RTF_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RTF_ERR_HIP;
+    if (h_nodes && hipMemcpy(h_nodes, f->nodes, sizeof(Node) * (size_t)f->n_total,
+                             hipMemcpyDeviceToHost) != hipSuccess)
+        return RTF_ERR_HIP;
+    if (h_table && hipMemcpy(h_table, f->table, sizeof(int32_t) * (size_t)f->m_total,
+                             hipMemcpyDeviceToHost) != hipSuccess)
+        return RTF_ERR_HIP;
+    if (h_W) {
+        Dist *tmp = static_cast<Dist *>(malloc(sizeof(Dist) * (size_t)f->D));
+        if (!tmp) return RTF_ERR_INVALID_ARG;
+        hipError_t e = hipMemcpy(tmp, f->dists, sizeof(Dist) * (size_t)f->D,
+                                 hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            for (int32_t d = 0; d < f->D; ++d) h_W[d] = tmp[d].W;
+        free(tmp);
+        if (e != hipSuccess) return RTF_ERR_HIP;
+    }
+    return RTF_OK;
+}
+
+const char *rtf_status_string(rtf_status s) {
+    switch (s) {
+    case RTF_OK: return "RTF_OK";
+    case RTF_ERR_INVALID_ARG: return "RTF_ERR_INVALID_ARG";
+    case RTF_ERR_SIZE: return "RTF_ERR_SIZE";
+    case RTF_ERR_WORKSPACE: return "RTF_ERR_WORKSPACE";
+    case RTF_ERR_HIP: return "RTF_ERR_HIP";
+    case RTF_ERR_ZERO_TOTAL: return "RTF_ERR_ZERO_TOTAL";
+    case RTF_ERR_VALUE: return "RTF_ERR_VALUE";
+    }
+    return "RTF_ERR_UNKNOWN";
+}
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// rtf_backward.hip -- adjoint of the continuous position x (Sec. 5) with
+// respect to the real weights v = q / scale, the sampled index held fixed.
+//
+// For sample s of distribution d with index i, xi = u 2^-64 and
+// frac = ((t - C_i) + lo 2^-64) / w_i, x = (i + frac) / n_d with
+// frac = (xi W - C_i) / w_i, so
+//   dx/dv_k = (xi - [k < i] - [k == i] frac) / (n_d w_i)      (w in real units)
+// and with a_s = g_s / (n_d w_{i_s}):
+//   dL/dv_k = A_d - sum_{j > k} B_j - D_k,
+//   A_d = sum_s a_s xi_s,  B_j = sum_{i_s = j} a_s,  D_j = sum_{i_s = j} a_s frac_s.
+// k_bscatter accumulates A, B, D with FP64 atomics; k_bcombine does the
+// segmented suffix sum of B per distribution.
+#include "rtf_internal.h"
+
+namespace rtf {
+
+namespace {
+
+constexpr int BB = 256;
+constexpr int CHUNK = BB * 32;  // samples per scatter block
+
+__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
+    int32_t lo = 0, hi = D;
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_bzero(double *B, double *Dv, int64_t n, double *A, int32_t D) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        B[i] = 0.0;
+        Dv[i] = 0.0;
+        if (i < D) A[i] = 0.0;
+    }
+}
+
+__device__ inline double block_sum(double x, double *s_red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) s_red[w] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < BB / 64; ++i) t += s_red[i];
+    __syncthreads();
+    return t;  // valid in thread 0
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(BB) void k_bscatter(const Node *__restrict__ nodes,
+                                                 const Dist *__restrict__ dists, int32_t D,
+                                                 const int64_t *__restrict__ soff,
+                                                 const uint64_t *__restrict__ u,
+                                                 const int32_t *__restrict__ idx,
+                                                 const double *__restrict__ gx, int64_t S,
+                                                 const double *__restrict__ scale, double *B,
+                                                 double *Dv, double *A) {
+    __shared__ double s_red[BB / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * CHUNK;
+    const int64_t c1 = c0 + CHUNK < S ? c0 + CHUNK : S;
+    const int32_t d_first = BATCHED ? find_segment(soff, D, c0) : 0;
+    const int32_t d_last = BATCHED ? find_segment(soff, D, c1 - 1) : 0;
+    const bool uniform = d_first == d_last;
+    int32_t d = d_first;
+    int64_t dend = BATCHED ? soff[d + 1] : S;
+    double acc = 0.0;
+    for (int64_t s = c0 + threadIdx.x; s < c1; s += BB) {
+        if (BATCHED && s >= dend) {
+            if (acc != 0.0) unsafeAtomicAdd(A + d, acc);
+            acc = 0.0;
+            d = find_segment(soff, D, s);
+            dend = soff[d + 1];
+        }
+        const int32_t li = idx[s];
+        const Dist &P = dists[d];
+        if (li < 0 || li >= P.n || (P.flags & DIST_ZERO)) continue;
+        const int64_t i = P.eo + li;
+        const uint64_t W = P.W, us = u[s];
+        const uint64_t Ci = mulhi64(nodes[i].key, W);
+        uint64_t Cn = W;
+        if (i + 1 < P.eo + P.n) {
+            const uint64_t k1 = nodes[i + 1].key;
+            if (k1 != ~0ull) Cn = mulhi64(k1, W);
+        }
+        const uint64_t t = mulhi64(us, W), lo = us * W;
+        const double wi = (double)(Cn - Ci);
+        const double frac = ((double)(t - Ci) + ldexp((double)lo, -64)) / wi;
+        const double xi = ldexp((double)us, -64);
+        const double a = gx[s] / ((double)P.n * (wi / scale[d]));
+        acc += a * xi;
+        unsafeAtomicAdd(B + i, a);
+        unsafeAtomicAdd(Dv + i, a * frac);
+    }
+    if (uniform) {
+        const double t = block_sum(acc, s_red);
+        if (threadIdx.x == 0 && t != 0.0) unsafeAtomicAdd(A + d_first, t);
+    } else if (acc != 0.0) {
+        unsafeAtomicAdd(A + d, acc);
+    }
+}
+
+// One block per distribution: grad[k] = A - sum_{j>k} B_j - D_k, scanning the
+// distribution from its end in chunks of BB elements.
+__global__ __launch_bounds__(BB) void k_bcombine(const Dist *__restrict__ dists,
+                                                 const double *__restrict__ B,
+                                                 const double *__restrict__ Dv,
+                                                 const double *__restrict__ A,
+                                                 double *__restrict__ grad) {
+    __shared__ double s_w[BB / 64];
+    const Dist P = dists[blockIdx.x];
+    const double Ad = A[blockIdx.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double carry = 0.0;  // sum of B over elements after the current chunk
+    for (int64_t end = P.eo + P.n; end > P.eo; end -= BB) {
+        // element handled by this thread: end-1-threadIdx.x (reverse order)
+        const int64_t k = end - 1 - threadIdx.x;
+        const bool ok = k >= P.eo;
+        const double b = ok ? B[k] : 0.0;
+        // inclusive scan over threads in reverse element order
+        double x = b;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            double y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        double off = 0.0, tot = 0.0;
+#pragma unroll
+        for (int i = 0; i < BB / 64; ++i) {
+            off += (i < w) ? s_w[i] : 0.0;
+            tot += s_w[i];
+        }
+        __syncthreads();
+        // exclusive sum of B over elements right of k
+        const double right = carry + off + x - b;
+        if (ok) grad[k] = Ad - right - Dv[k];
+        carry += tot;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_backward(const Node *nodes, const Dist *dists, int32_t D, int64_t n_total,
+                           const int64_t *sample_off, const uint64_t *u, const int32_t *idx,
+                           const double *gx, int64_t S, const double *scale, double *grad_w,
+                           double *wsB, double *wsDv, double *wsA, hipStream_t st) {
+    int64_t zb = (n_total + 255) / 256;
+    if (zb > 4096) zb = 4096;
+    hipLaunchKernelGGL(k_bzero, dim3((unsigned)zb), dim3(256), 0, st, wsB, wsDv, n_total, wsA,
+                       D);
+    if (S > 0) {
+        const int64_t nb = (S + CHUNK - 1) / CHUNK;
+        if (sample_off)
+            hipLaunchKernelGGL(k_bscatter<true>, dim3((unsigned)nb), dim3(BB), 0, st, nodes, dists,
+                               D, sample_off, u, idx, gx, S, scale, wsB, wsDv, wsA);
+        else
+            hipLaunchKernelGGL(k_bscatter<false>, dim3((unsigned)nb), dim3(BB), 0, st, nodes, dists,
+                               D, sample_off, u, idx, gx, S, scale, wsB, wsDv, wsA);
+    }
+    hipLaunchKernelGGL(k_bcombine, dim3((unsigned)D), dim3(BB), 0, st, dists, wsB, wsDv, wsA,
+                       grad_w);
+    return hipGetLastError();
+}
+
+}  // namespace rtf

@@ -1,0 +1,709 @@
+// rtf_build.hip -- parallel construction of the guide table and radix tree
+// forest (Binder & Keller, Sec. 3.1-3.2, Alg. 1; many distributions: Sec. 5).
+//
+// The forest is the unique tree Alg. 1 builds from the per-boundary levels
+// (position of the highest differing bit of neighbouring fixed-point lower
+// bounds, or SENT where merges may not cross): within a cell, the root of a
+// leaf range is its boundary of highest level (the rightmost one on a tie),
+// which is what Alg. 1's bottom-up merges produce under every schedule.  Alg.
+// 1 finds it with an atomic exchange per merge; here each node instead finds
+// the two boundaries of higher level that enclose it (its subtree) by a short
+// scan over the levels held in LDS, and writes its own 16-byte record once.
+// With m proportional to n the cells hold a few leaves, so the scans are a few
+// LDS reads; scans that leave a tile's LDS window or exceed SCAN_CAP steps are
+// finished by a fix-up kernel that uses binary searches on the global keys.
+//
+// Kernels (stream order):
+//   k_offsets    copy offsets into the workspace, clear the status word
+//   k_tile_sums  per-tile weight sums (+ in-tile prefix at distribution starts)
+//   k_dist_params  scan of tile sums; per distribution W, reciprocal, G0
+//   k_build_tile keys, levels, node records, guide-table entries per tile
+//   k_fixup      deferred node records and long guide-table runs
+#include "rtf_internal.h"
+
+namespace rtf {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ inline uint64_t wave_incl_scan(uint64_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ inline uint64_t wave_incl_suffix(uint64_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_down(x, o, 64);
+        if (lane + o < 64) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan over the block (NW waves); returns the thread's exclusive
+// prefix and the block total.
+template <int NW>
+__device__ inline uint64_t block_excl_scan(uint64_t x, uint64_t *s_wave, uint64_t &total) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint64_t inc = wave_incl_scan(x);
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        uint64_t v = s_wave[i];
+        off += (i < w) ? v : 0;
+        tot += v;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - x;
+}
+
+// index d with off[d] <= i < off[d+1] over off[0..D]
+__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
+    int32_t lo = 0, hi = D;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline void load16(const uint32_t *w, int64_t i0, int64_t n, bool vec, uint32_t *r) {
+    if (vec && i0 + ITEMS <= n) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(w + i0);
+#pragma unroll
+        for (int q = 0; q < ITEMS / 4; ++q) {
+            uint4 v = p[q];
+            r[4 * q + 0] = v.x;
+            r[4 * q + 1] = v.y;
+            r[4 * q + 2] = v.z;
+            r[4 * q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e) r[e] = (i0 + e < n) ? w[i0 + e] : 0u;
+    }
+}
+
+// Leaf description used for levels: key and global cell; cell -1 marks a leaf
+// past its distribution's last positive weight, -2 a position outside [0, n).
+struct Leaf {
+    uint64_t key;
+    int32_t cell;
+};
+
+__device__ inline int level_between(const Leaf &a, const Leaf &b) {
+    if (a.cell < 0 || b.cell < 0 || a.cell != b.cell) return SENT;
+    return level_of(a.key, b.key);
+}
+
+__device__ inline Leaf make_leaf(uint64_t C, const Dist &P) {
+    Leaf L;
+    if (C < P.W) {
+        L.key = fixed_point_key(C, P.W << P.s, P.v, P.s);
+        L.cell = (int32_t)(P.co + (int64_t)mulhi64(L.key, (uint64_t)P.m));
+    } else {
+        L.key = ~0ull;
+        L.cell = -1;
+    }
+    return L;
+}
+
+__device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t c0, int32_t c1) {
+    uint4 v;
+    v.x = (uint32_t)key;
+    v.y = (uint32_t)(key >> 32);
+    v.z = (uint32_t)c0;
+    v.w = (uint32_t)c1;
+    *reinterpret_cast<uint4 *>(nodes + j) = v;
+}
+
+// ---------------------------------------------------------------------------
+// k_offsets
+// ---------------------------------------------------------------------------
+__global__ void k_offsets(const int64_t *src_e, const int64_t *src_c, int64_t *dst_e,
+                          int64_t *dst_c, int32_t D, int64_t n, int64_t m, uint32_t *status) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) *status = 0u;
+    if (t > D) return;
+    if (src_e) {
+        dst_e[t] = src_e[t];
+        dst_c[t] = src_c[t];
+    } else {  // one distribution
+        dst_e[t] = t ? n : 0;
+        dst_c[t] = t ? m : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_tile_sums: the prefix-sum pass over the weights (Sec. 2.6 notes that the
+// prefix sum of an inversion method computes efficiently in parallel)
+// ---------------------------------------------------------------------------
+template <bool BATCHED>
+__global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
+    __shared__ uint64_t s_wave[BT / 64];
+    __shared__ uint64_t s_thr[BT];
+    const int64_t t = blockIdx.x;
+    const int64_t base = t * TILE;
+    const int64_t i0 = base + (int64_t)threadIdx.x * ITEMS;
+    uint32_t r[ITEMS];
+    load16(a.w, i0, a.n_total, vec, r);
+    uint64_t sum = 0;
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e) sum += r[e];
+    uint64_t total;
+    uint64_t ex = block_excl_scan<BT / 64>(sum, s_wave, total);
+    if (threadIdx.x == 0) a.tile_sum[t] = total;
+    if (!BATCHED) return;
+    s_thr[threadIdx.x] = ex;
+    __syncthreads();
+    // distributions that start inside this tile: record the in-tile prefix
+    const int64_t end = base + TILE;
+    int32_t dlo;
+    {
+        int32_t lo = 0, hi = a.D;  // first d with elem_off[d] >= base
+        while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if (a.elem_off[mid] < base) lo = mid + 1;
+            else hi = mid;
+        }
+        dlo = lo;
+    }
+    for (int32_t d = dlo + threadIdx.x; d < a.D; d += BT) {
+        int64_t e = a.elem_off[d];
+        if (e >= end) break;
+        int64_t off = e - base;
+        int64_t tq = off / ITEMS;
+        uint64_t L = s_thr[tq];
+        for (int64_t q = base + tq * ITEMS; q < e; ++q) L += a.w[q];
+        a.dist_local[d] = L;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_dist_params: one block.  Exclusive scan of the tile sums, then per
+// distribution the total W, the divisor normalisation and reciprocal, and the
+// global prefix at its first element.
+// ---------------------------------------------------------------------------
+constexpr int PT = 1024;
+template <bool BATCHED>
+__global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
+    __shared__ uint64_t s_wave[PT / 64];
+    const int64_t nt = a.ntiles;
+    const int64_t per = (nt + PT - 1) / PT;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    const int64_t hi = lo + per < nt ? lo + per : nt;
+    uint64_t sum = 0;
+    for (int64_t q = lo; q < hi; ++q) sum += a.tile_sum[q];
+    uint64_t total;
+    uint64_t run = block_excl_scan<PT / 64>(sum, s_wave, total);
+    for (int64_t q = lo; q < hi; ++q) {
+        a.tile_prefix[q] = run;
+        run += a.tile_sum[q];
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int32_t d = threadIdx.x; d < a.D; d += PT) {
+        int64_t eo = a.elem_off[d], e1 = a.elem_off[d + 1];
+        uint64_t G0 = 0, G1 = total;
+        if (BATCHED) {
+            G0 = a.tile_prefix[eo / TILE] + a.dist_local[d];
+            if (d + 1 < a.D) G1 = a.tile_prefix[e1 / TILE] + a.dist_local[d + 1];
+        }
+        Dist P;
+        P.W = G1 - G0;
+        P.G0 = G0;
+        P.eo = eo;
+        P.n = e1 - eo;
+        P.co = a.cell_off[d];
+        P.m = a.cell_off[d + 1] - P.co;
+        P.flags = 0;
+        if (P.W == 0) {
+            P.s = 0;
+            P.v = 0;
+            P.flags = DIST_ZERO;
+            atomicOr(a.status, status_bit(RTF_ERR_ZERO_TOTAL));
+        } else {
+            P.s = (uint32_t)clz64(P.W);
+            P.v = reciprocal_2by1(P.W << P.s);
+        }
+        a.dists[d] = P;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_build_tile
+// ---------------------------------------------------------------------------
+constexpr int LVL_N = TILE + 2 * HALO;  // boundaries base-HALO .. base+TILE+HALO-2
+
+struct TileSmem {
+    uint8_t lvl[LVL_N];
+    uint64_t first_key[BT];
+    int32_t first_cell[BT];
+    uint64_t last_key[BT];
+    int32_t last_cell[BT];
+    uint64_t hkey[2 * HALO];
+    int32_t hcell[2 * HALO];
+    uint64_t wave[BT / 64];
+    int32_t ndefer;
+    int64_t items[DEFER_CAP];
+};
+
+__device__ inline void push_item(TileSmem &sm, int64_t item) {
+    int32_t k = atomicAdd(&sm.ndefer, 1);
+    if (k < DEFER_CAP) sm.items[k] = item;
+}
+
+// Left child of the node at boundary k with level l: the root of leaves
+// [L+1, k], where L is the nearest boundary left of k with a level above l.
+// Scanning leftwards, the first maximum met is the rightmost one.
+__device__ inline bool scan_left(const uint8_t *lvl, int64_t lb0, int64_t k, int l,
+                                 int32_t &ref) {
+    int64_t b = k - 1;
+    int best = -1;
+    int64_t bestb = -1;
+    for (int steps = 0;; ++steps) {
+        if (b < lb0 || steps >= SCAN_CAP) return false;
+        int lb = lvl[b - lb0];
+        if (lb > l) break;
+        if (lb > best) {
+            best = lb;
+            bestb = b;
+        }
+        --b;
+    }
+    ref = (best < 0) ? ~(int32_t)k : (int32_t)(bestb + 1);
+    return true;
+}
+
+// Right child: the root of leaves [k1, R], R the nearest boundary at or right
+// of k1 with a level >= l.  Scanning rightwards, ties move to the right.
+__device__ inline bool scan_right(const uint8_t *lvl, int64_t lb0, int64_t lb1, int64_t k1,
+                                  int l, int32_t &ref) {
+    int64_t b = k1;
+    int best = -1;
+    int64_t bestb = -1;
+    for (int steps = 0;; ++steps) {
+        if (b > lb1 || steps >= SCAN_CAP) return false;
+        int lb = lvl[b - lb0];
+        if (lb >= l) break;
+        if (lb >= best) {
+            best = lb;
+            bestb = b;
+        }
+        ++b;
+    }
+    ref = (best < 0) ? ~(int32_t)k1 : (int32_t)(bestb + 1);
+    return true;
+}
+
+__device__ inline void fill_run(int32_t *table, int64_t c_lo, int64_t c_hi, int32_t val) {
+    for (int64_t c = c_lo; c < c_hi; ++c) table[c] = val;
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
+    __shared__ TileSmem sm;
+    const int tid = threadIdx.x;
+    const int64_t t = blockIdx.x;
+    const int64_t base = t * TILE;
+    const int64_t i0 = base + (int64_t)tid * ITEMS;
+    const int64_t n = a.n_total;
+    const int64_t lb0 = base - HALO;             // lowest boundary held
+    const int64_t lb1 = base + TILE + HALO - 2;  // highest boundary held
+    if (tid == 0) sm.ndefer = 0;
+
+    // 1. weights and the global prefix of each element
+    uint32_t wv[ITEMS];
+    load16(a.w, i0, n, vec, wv);
+    uint64_t sum = 0;
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e) sum += wv[e];
+    uint64_t tile_total;
+    const uint64_t tp = a.tile_prefix[t];
+    uint64_t G = tp + block_excl_scan<BT / 64>(sum, sm.wave, tile_total);
+
+    // 2. keys and cells of the owned leaves
+    uint64_t key[ITEMS];
+    int32_t cell[ITEMS];
+    int32_t dcur = 0;
+    if (BATCHED) dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
+    Dist P = a.dists[dcur];
+    int64_t dend = P.eo + P.n;
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e) {
+        const int64_t i = i0 + e;
+        if (i < n) {
+            if (BATCHED) {
+                while (i >= dend) {
+                    ++dcur;
+                    P = a.dists[dcur];
+                    dend = P.eo + P.n;
+                }
+            }
+            Leaf L = make_leaf(G - P.G0, P);
+            key[e] = L.key;
+            cell[e] = L.cell;
+        } else {
+            key[e] = 0;
+            cell[e] = -2;
+        }
+        G += wv[e];
+    }
+    sm.first_key[tid] = key[0];
+    sm.first_cell[tid] = cell[0];
+    sm.last_key[tid] = key[ITEMS - 1];
+    sm.last_cell[tid] = cell[ITEMS - 1];
+
+    // 3. halo leaves: lanes 0..31 of wave 0 the HALO leaves left of the tile,
+    //    lanes 32..63 the HALO leaves right of it
+    if (tid < 64) {
+        const bool left = tid < HALO;
+        const int64_t i = left ? base - HALO + tid : base + TILE + (tid - HALO);
+        const bool exists = i >= 0 && i < n;
+        uint64_t wi = exists ? a.w[i] : 0u;
+        uint64_t suf = wave_incl_suffix(left ? wi : 0);
+        uint64_t pre = wave_incl_scan(left ? 0 : wi);
+        Leaf L;
+        L.key = 0;
+        L.cell = -2;
+        if (exists) {
+            uint64_t Gi = left ? tp - suf : tp + tile_total + pre - wi;
+            int32_t d = BATCHED ? find_segment(a.elem_off, a.D, i) : 0;
+            L = make_leaf(Gi - a.dists[d].G0, a.dists[d]);
+        }
+        sm.hkey[tid] = L.key;
+        sm.hcell[tid] = L.cell;
+    }
+    __syncthreads();
+
+    // 4. levels of all boundaries held in LDS
+    {
+        Leaf nxt;
+        if (tid + 1 < BT) {
+            nxt.key = sm.first_key[tid + 1];
+            nxt.cell = sm.first_cell[tid + 1];
+        } else {
+            nxt.key = sm.hkey[HALO];
+            nxt.cell = sm.hcell[HALO];
+        }
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e) {
+            Leaf A{key[e], cell[e]};
+            Leaf B = (e + 1 < ITEMS) ? Leaf{key[e + 1], cell[e + 1]} : nxt;
+            sm.lvl[(i0 + e) - lb0] = (uint8_t)level_between(A, B);
+        }
+        if (tid < HALO) {  // boundaries base-HALO+tid, between halo leaves / tile leaf 0
+            Leaf A{sm.hkey[tid], sm.hcell[tid]};
+            Leaf B = (tid + 1 < HALO) ? Leaf{sm.hkey[tid + 1], sm.hcell[tid + 1]}
+                                      : Leaf{sm.first_key[0], sm.first_cell[0]};
+            sm.lvl[tid] = (uint8_t)level_between(A, B);
+        } else if (tid < 2 * HALO - 1) {  // boundaries base+TILE+(tid-HALO)
+            Leaf A{sm.hkey[tid], sm.hcell[tid]};
+            Leaf B{sm.hkey[tid + 1], sm.hcell[tid + 1]};
+            sm.lvl[TILE + tid] = (uint8_t)level_between(A, B);
+        }
+    }
+    __syncthreads();
+
+    // 5. node records and guide-table entries of the owned nodes
+    Leaf prev;  // leaf i0 - 1
+    if (tid > 0) {
+        prev.key = sm.last_key[tid - 1];
+        prev.cell = sm.last_cell[tid - 1];
+    } else {
+        prev.key = sm.hkey[HALO - 1];
+        prev.cell = sm.hcell[HALO - 1];
+    }
+    Leaf nxt;  // leaf i0 + ITEMS
+    if (tid + 1 < BT) {
+        nxt.key = sm.first_key[tid + 1];
+        nxt.cell = sm.first_cell[tid + 1];
+    } else {
+        nxt.key = sm.hkey[HALO];
+        nxt.cell = sm.hcell[HALO];
+    }
+    if (BATCHED) {
+        dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
+        P = a.dists[dcur];
+        dend = P.eo + P.n;
+    }
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e) {
+        const int64_t j = i0 + e;
+        if (j >= n) break;
+        if (BATCHED) {
+            while (j >= dend) {
+                ++dcur;
+                P = a.dists[dcur];
+                dend = P.eo + P.n;
+            }
+        }
+        const int32_t pcell = (e > 0) ? cell[e - 1] : prev.cell;
+        const Leaf nx = (e + 1 < ITEMS) ? Leaf{key[e + 1], cell[e + 1]} : nxt;
+        const int l = sm.lvl[(j - 1) - lb0];
+        int32_t c0 = ~(int32_t)j, c1 = ~(int32_t)j;
+        bool ok = true;
+        if (cell[e] >= 0) {
+            if (l == SENT) {
+                // first node of a cell: child 1 roots the cell's tree, child 0
+                // is the interval overlapping the cell from the left
+                c0 = (key[e] == 0) ? ~(int32_t)j : ~(int32_t)(j - 1);
+                ok = scan_right(sm.lvl, lb0, lb1, j, SENT, c1);
+                a.table[cell[e]] = (int32_t)j;
+                if (key[e] != 0 && cell[e] - pcell > 1) {
+                    if (cell[e] - pcell - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_HEAD);
+                    else fill_run(a.table, pcell + 1, cell[e], ~(int32_t)(j - 1));
+                }
+            } else {
+                ok = scan_left(sm.lvl, lb0, j - 1, l, c0);
+                ok = ok && scan_right(sm.lvl, lb0, lb1, j, l, c1);
+            }
+            // the distribution's last leaf with mass covers the remaining cells
+            if (nx.cell < 0 || (nx.key == 0 && nx.cell != cell[e])) {
+                const int64_t cend = P.co + P.m;
+                if (cend - cell[e] > 1) {
+                    if (cend - cell[e] - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_TAIL);
+                    else fill_run(a.table, cell[e] + 1, cend, ~(int32_t)j);
+                }
+            }
+        }
+        if (ok) {
+            store_node(a.nodes, j, key[e], c0, c1);
+        } else {
+            a.nodes[j].key = key[e];
+            push_item(sm, (j << 2) | ITEM_NODE);
+        }
+    }
+    __syncthreads();
+    const int32_t nd = sm.ndefer;
+    if (tid == 0) a.defer_count[t] = nd;
+    const int32_t nk = nd < DEFER_CAP ? nd : DEFER_CAP;
+    for (int32_t k = tid; k < nk; k += BT) a.defer_items[t * DEFER_CAP + k] = sm.items[k];
+}
+
+// ---------------------------------------------------------------------------
+// k_fixup: the deferred work, from the keys in global memory
+// ---------------------------------------------------------------------------
+template <bool BATCHED>
+struct GlobalView {
+    const BuildArgs &a;
+    __device__ GlobalView(const BuildArgs &args) : a(args) {}
+    __device__ int32_t dist_of(int64_t i) const {
+        return BATCHED ? find_segment(a.elem_off, a.D, i) : 0;
+    }
+    __device__ Leaf leaf(int64_t i) const {
+        Leaf L;
+        L.key = 0;
+        L.cell = -2;
+        if (i < 0 || i >= a.n_total) return L;
+        L.key = a.nodes[i].key;
+        if (L.key == ~0ull) {
+            L.cell = -1;
+            return L;
+        }
+        const Dist &P = a.dists[dist_of(i)];
+        L.cell = (int32_t)(P.co + (int64_t)mulhi64(L.key, (uint64_t)P.m));
+        return L;
+    }
+    __device__ int level(int64_t b) const { return level_between(leaf(b), leaf(b + 1)); }
+    // leaf x lies in the subtree range of a leaf with key kk in cell c at level l
+    __device__ bool in_range(int64_t x, uint64_t kk, int32_t c, int l) const {
+        Leaf L = leaf(x);
+        if (L.cell != c) return false;
+        if (l >= 64) return true;
+        return ((L.key ^ kk) >> l) == 0;
+    }
+    // smallest a <= k with in_range on [a, k] (in_range(k) holds)
+    __device__ int64_t extend_left(int64_t k, uint64_t kk, int32_t c, int l) const {
+        int64_t good = k, bad = -1;
+        for (int64_t dd = 1;; dd <<= 1) {
+            int64_t x = k - dd;
+            if (x < 0 || !in_range(x, kk, c, l)) {
+                bad = x < -1 ? -1 : x;
+                break;
+            }
+            good = x;
+        }
+        while (good - bad > 1) {
+            int64_t mid = bad + (good - bad) / 2;
+            if (in_range(mid, kk, c, l)) good = mid;
+            else bad = mid;
+        }
+        return good;
+    }
+    // largest b >= k with in_range on [k, b] (in_range(k) holds)
+    __device__ int64_t extend_right(int64_t k, uint64_t kk, int32_t c, int l) const {
+        int64_t good = k, bad = a.n_total;
+        for (int64_t dd = 1;; dd <<= 1) {
+            int64_t x = k + dd;
+            if (x >= a.n_total || !in_range(x, kk, c, l)) {
+                bad = x > a.n_total ? a.n_total : x;
+                break;
+            }
+            good = x;
+        }
+        while (bad - good > 1) {
+            int64_t mid = good + (bad - good) / 2;
+            if (in_range(mid, kk, c, l)) good = mid;
+            else bad = mid;
+        }
+        return good;
+    }
+    // root of the subtree over leaves [lo, hi] of one cell: the boundary of
+    // highest level, where the highest bit in which key_lo and key_hi differ
+    // turns from 0 to 1 (the rightmost boundary if all keys are equal)
+    __device__ int32_t root(int64_t lo, int64_t hi) const {
+        if (lo == hi) return ~(int32_t)lo;
+        uint64_t klo = a.nodes[lo].key, khi = a.nodes[hi].key;
+        int lam = level_of(klo, khi);
+        if (lam == 0) return (int32_t)hi;
+        const int bit = lam - 1;
+        int64_t g = lo, b = hi;  // bit clear at g, set at b
+        while (b - g > 1) {
+            int64_t mid = g + (b - g) / 2;
+            if ((a.nodes[mid].key >> bit) & 1) b = mid;
+            else g = mid;
+        }
+        return (int32_t)(g + 1);
+    }
+    // the record of node j
+    __device__ void node(int64_t j, uint64_t &kj, int32_t &c0, int32_t &c1) const {
+        Leaf Lj = leaf(j);
+        kj = Lj.key;
+        c0 = c1 = ~(int32_t)j;
+        if (Lj.cell < 0) return;
+        Leaf Lp = leaf(j - 1);
+        int l = level_between(Lp, Lj);
+        if (l == SENT) {
+            c0 = (Lj.key == 0) ? ~(int32_t)j : ~(int32_t)(j - 1);
+            int64_t b = extend_right(j, Lj.key, Lj.cell, 64);
+            c1 = root(j, b);
+        } else {
+            const int64_t k = j - 1;
+            int64_t lo = extend_left(k, Lp.key, Lp.cell, l);
+            int64_t hi = (l == 0) ? j : extend_right(j, Lp.key, Lp.cell, l);
+            c0 = root(lo, k);
+            c1 = root(j, hi);
+        }
+    }
+    // guide-table runs owned by node / leaf j: [lo, hi) filled with val
+    __device__ bool head_run(int64_t j, int64_t &lo, int64_t &hi, int32_t &val) const {
+        Leaf Lj = leaf(j), Lp = leaf(j - 1);
+        if (Lj.cell < 0 || Lj.key == 0 || level_between(Lp, Lj) != SENT) return false;
+        lo = (int64_t)Lp.cell + 1;
+        hi = Lj.cell;
+        val = ~(int32_t)(j - 1);
+        return hi > lo;
+    }
+    __device__ bool tail_run(int64_t j, int64_t &lo, int64_t &hi, int32_t &val) const {
+        Leaf Lj = leaf(j), Ln = leaf(j + 1);
+        if (Lj.cell < 0) return false;
+        if (!(Ln.cell < 0 || (Ln.key == 0 && Ln.cell != Lj.cell))) return false;
+        const Dist &P = a.dists[dist_of(j)];
+        lo = (int64_t)Lj.cell + 1;
+        hi = P.co + P.m;
+        val = ~(int32_t)j;
+        return hi > lo;
+    }
+};
+
+template <bool BATCHED>
+__global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
+    __shared__ int64_t s_item[DEFER_CAP];
+    __shared__ int32_t s_nrun;
+    __shared__ int64_t s_run[3];
+    const int64_t t = blockIdx.x;
+    const int32_t cnt = a.defer_count[t];
+    if (cnt == 0) return;
+    GlobalView<BATCHED> gv(a);
+    const int64_t base = t * TILE;
+    if (cnt > DEFER_CAP) {
+        // too many deferrals: redo every node and table run of the tile
+        for (int64_t j = base + threadIdx.x; j < base + TILE && j < a.n_total; j += BT) {
+            uint64_t kj;
+            int32_t c0, c1;
+            gv.node(j, kj, c0, c1);
+            store_node(a.nodes, j, kj, c0, c1);
+            int64_t lo, hi;
+            int32_t val;
+            if (gv.head_run(j, lo, hi, val)) fill_run(a.table, lo, hi, val);
+            if (gv.tail_run(j, lo, hi, val)) fill_run(a.table, lo, hi, val);
+        }
+        return;
+    }
+    if (threadIdx.x == 0) s_nrun = 0;
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < cnt; k += BT) {
+        int64_t it = a.defer_items[t * DEFER_CAP + k];
+        int64_t j = it >> 2;
+        if ((it & 3) == ITEM_NODE) {
+            uint64_t kj;
+            int32_t c0, c1;
+            gv.node(j, kj, c0, c1);
+            store_node(a.nodes, j, kj, c0, c1);
+        } else {
+            s_item[atomicAdd(&s_nrun, 1)] = it;
+        }
+    }
+    __syncthreads();
+    const int32_t nr = s_nrun;
+    for (int32_t r = 0; r < nr; ++r) {
+        if (threadIdx.x == 0) {
+            int64_t it = s_item[r], lo = 0, hi = 0;
+            int32_t val = 0;
+            bool has = ((it & 3) == ITEM_HEAD) ? gv.head_run(it >> 2, lo, hi, val)
+                                               : gv.tail_run(it >> 2, lo, hi, val);
+            s_run[0] = has ? lo : 0;
+            s_run[1] = has ? hi : 0;
+            s_run[2] = val;
+        }
+        __syncthreads();
+        const int64_t lo = s_run[0], hi = s_run[1];
+        const int32_t val = (int32_t)s_run[2];
+        for (int64_t c = lo + threadIdx.x; c < hi; c += BT) a.table[c] = val;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_copy_offsets(const int64_t *src_e, const int64_t *src_c, int64_t *dst_e,
+                               int64_t *dst_c, int32_t D, int64_t n, int64_t m,
+                               uint32_t *status, hipStream_t st) {
+    int64_t cnt = (int64_t)D + 1;
+    int blocks = (int)((cnt + 255) / 256);
+    hipLaunchKernelGGL(k_offsets, dim3(blocks), dim3(256), 0, st, src_e, src_c, dst_e, dst_c,
+                       D, n, m, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
+    const bool vec = (reinterpret_cast<uintptr_t>(a.w) & 15) == 0;
+    const dim3 grid((unsigned)a.ntiles);
+    if (a.D > 1) {
+        hipLaunchKernelGGL(k_tile_sums<true>, grid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL(k_dist_params<true>, dim3(1), dim3(PT), 0, st, a);
+        hipLaunchKernelGGL(k_build_tile<true>, grid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL(k_fixup<true>, grid, dim3(BT), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_tile_sums<false>, grid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL(k_dist_params<false>, dim3(1), dim3(PT), 0, st, a);
+        hipLaunchKernelGGL(k_build_tile<false>, grid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL(k_fixup<false>, grid, dim3(BT), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rtf

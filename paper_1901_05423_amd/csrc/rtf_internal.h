@@ -1,0 +1,151 @@
+// rtf_internal.h -- shared definitions of the HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rtforest.h"
+
+namespace rtf {
+
+// A level above every real one (0..64): a boundary merges never cross, used
+// for cell changes, distribution changes, both array ends and the end of the
+// weights that carry mass (Alg. 1 sets the neighbour "to the maximum").
+constexpr int SENT = 65;
+
+// Build tile: 256 threads x 16 consecutive elements.
+constexpr int BT = 256;
+constexpr int ITEMS = 16;
+constexpr int TILE = BT * ITEMS;
+// Leaves on either side of a tile whose keys are recomputed locally so that
+// subtree scans near the tile edges stay in LDS.
+constexpr int HALO = 32;
+// Longest in-LDS subtree scan; longer ones are finished by the fix-up kernel.
+constexpr int SCAN_CAP = 64;
+// Longest guide-table run written by one lane; longer ones go to the fix-up.
+constexpr int RUN_CAP = 64;
+// Deferred items kept per tile; more make the fix-up redo the whole tile.
+constexpr int DEFER_CAP = 512;
+
+// deferred item kinds (low 2 bits of an item)
+constexpr int64_t ITEM_NODE = 0;  // node record j
+constexpr int64_t ITEM_HEAD = 1;  // empty cells before cell-start leaf j
+constexpr int64_t ITEM_TAIL = 2;  // empty cells after the last leaf j
+
+struct alignas(16) Node {
+    uint64_t key;
+    int32_t c0, c1;
+};
+
+// Per-distribution parameters, written by the build's scan kernel.
+struct alignas(64) Dist {
+    uint64_t W;   // total weight
+    uint64_t v;   // reciprocal of the normalised divisor W << s
+    uint64_t G0;  // global prefix sum at the distribution's first element
+    int64_t eo;   // first element
+    int64_t n;    // elements
+    int64_t co;   // first guide cell
+    int64_t m;    // guide cells
+    uint32_t s;   // clz(W)
+    uint32_t flags;
+};
+constexpr uint32_t DIST_ZERO = 1u;
+
+// status word bits: 1 << rtf_status
+__host__ __device__ inline uint32_t status_bit(int code) { return 1u << code; }
+
+struct BuildArgs {
+    const uint32_t *w;
+    const int64_t *elem_off;  // workspace copy, D+1
+    const int64_t *cell_off;  // workspace copy, D+1
+    int32_t D;
+    int64_t n_total;
+    int64_t m_total;
+    int64_t ntiles;
+    Node *nodes;
+    int32_t *table;
+    Dist *dists;
+    uint32_t *status;
+    uint64_t *tile_sum;     // [ntiles]
+    uint64_t *tile_prefix;  // [ntiles]
+    uint64_t *dist_local;   // [D]: in-tile prefix at each distribution start
+    int32_t *defer_count;   // [ntiles]
+    int64_t *defer_items;   // [ntiles * DEFER_CAP]
+};
+
+// ---- exact 64-bit fixed-point helpers ----------------------------------
+
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+}
+
+__host__ __device__ inline int clz64(uint64_t x) { return x ? __builtin_clzll(x) : 64; }
+
+// floor((2^128 - 1) / d) - 2^64 for a normalised d (top bit set): the
+// reciprocal of the 2-by-1 division of Moller and Granlund, "Improved
+// division by invariant integers" (IEEE Trans. Computers, 2011).  Computed by
+// restoring long division of (2^64 - 1 - d) * 2^64 + (2^64 - 1) by d.
+__host__ __device__ inline uint64_t reciprocal_2by1(uint64_t d) {
+    uint64_t hi = ~d, lo = ~0ull, q = 0;
+    for (int b = 0; b < 64; ++b) {
+        uint64_t top = hi >> 63;
+        hi = (hi << 1) | (lo >> 63);
+        lo <<= 1;
+        q <<= 1;
+        if (top || hi >= d) {
+            hi -= d;
+            q |= 1;
+        }
+    }
+    return q;
+}
+
+// Key U = ceil(C * 2^64 / W) for 0 <= C < W, given s = clz(W), d = W << s
+// and v = reciprocal_2by1(d): one 2-by-1 division (Moller-Granlund, Alg. 4)
+// of (C << s) * 2^64 by d, then rounding up on a non-zero remainder.
+__host__ __device__ inline uint64_t fixed_point_key(uint64_t C, uint64_t d, uint64_t v,
+                                                     uint32_t s) {
+    uint64_t u1 = C << s;  // < d
+    uint64_t q0 = v * u1;
+    uint64_t q1 = mulhi64(v, u1) + u1 + 1;
+    uint64_t r = 0 - q1 * d;
+    if (r > q0) {
+        q1 -= 1;
+        r += d;
+    }
+    if (r >= d) {
+        q1 += 1;
+        r -= d;
+    }
+    return q1 + (r != 0 ? 1 : 0);
+}
+
+// Level of the boundary between two neighbouring leaves: 64 - clz(a ^ b).
+__host__ __device__ inline int level_of(uint64_t a, uint64_t b) { return 64 - clz64(a ^ b); }
+
+// ---- launchers (defined in the .hip files) ----------------------------------
+
+hipError_t launch_build(const BuildArgs &a, hipStream_t st);
+hipError_t launch_sample(const Node *nodes, const int32_t *table, const Dist *dists,
+                         const int64_t *sample_off, int32_t D, int64_t n_total,
+                         const uint64_t *u, int64_t S, int32_t *idx, double *x,
+                         hipStream_t st);
+hipError_t launch_sample_2d(const Node *nodes, const int32_t *table, const Dist *dists,
+                            int32_t D, int64_t n_total, const uint64_t *u2, int64_t S,
+                            int32_t *rc, double *xy, hipStream_t st);
+hipError_t launch_sample_bsearch(const Node *nodes, const int32_t *table,
+                                 const Dist *dists, bool cutpoint, const uint64_t *u,
+                                 int64_t S, int32_t *idx, double *x, hipStream_t st);
+hipError_t launch_copy_offsets(const int64_t *src_e, const int64_t *src_c, int64_t *dst_e,
+                               int64_t *dst_c, int32_t D, int64_t n, int64_t m,
+                               uint32_t *status, hipStream_t st);
+hipError_t launch_quantize(const float *v, const int64_t *elem_off, int32_t D,
+                           int64_t n_total, uint32_t *out, double *scale,
+                           uint32_t *status, hipStream_t st);
+hipError_t launch_backward(const Node *nodes, const Dist *dists, int32_t D,
+                           int64_t n_total, const int64_t *sample_off, const uint64_t *u,
+                           const int32_t *idx, const double *gx, int64_t S,
+                           const double *scale, double *grad_w, double *wsB, double *wsDv,
+                           double *wsA, hipStream_t st);
+
+}  // namespace rtf

@@ -1,0 +1,121 @@
+// rtf_quantize.hip -- real weights to uint32, per distribution.
+//
+// The method needs exact partial sums; weights are therefore quantised before
+// the build: s_d = (2^32 - 1) / max_d v in FP64, q = rint(v * s_d) clamped to
+// [1, 2^32 - 1] for v > 0 and q = 0 for v == 0.  One FP64 multiply and a
+// round-half-even, so the result is the same on every IEEE machine.
+//
+// Kernels: k_qinit clears the per-distribution maxima (kept in the low word of
+// scale[d] while the call runs), k_qmax takes the maxima with integer atomics
+// on the float bits (order-preserving for non-negative floats), k_qapply
+// writes q, k_qfinal writes the scales.
+#include "rtf_internal.h"
+
+namespace rtf {
+
+namespace {
+
+constexpr int QT = 256;
+constexpr int QI = 16;
+
+__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
+    int32_t lo = 0, hi = D;
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline uint32_t *max_word(double *scale, int32_t d) {
+    return reinterpret_cast<uint32_t *>(scale + d);
+}
+
+__global__ void k_qinit(double *scale, int32_t D) {
+    int32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d < D) scale[d] = 0.0;
+}
+
+__global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
+                                             const int64_t *__restrict__ off, int32_t D,
+                                             int64_t n, double *scale, uint32_t *status) {
+    const int64_t i0 = ((int64_t)blockIdx.x * QT + threadIdx.x) * QI;
+    if (i0 >= n) return;
+    int32_t d = off ? find_segment(off, D, i0) : 0;
+    int64_t dend = off ? off[d + 1] : n;
+    uint32_t mx = 0;
+    bool bad = false;
+    for (int e = 0; e < QI && i0 + e < n; ++e) {
+        const int64_t i = i0 + e;
+        while (i >= dend) {
+            if (mx) atomicMax(max_word(scale, d), mx);
+            mx = 0;
+            ++d;
+            dend = off[d + 1];
+        }
+        const float x = v[i];
+        if (!(x >= 0.0f) || isinf(x)) {
+            bad = true;
+            continue;
+        }
+        const uint32_t b = __float_as_uint(x);
+        mx = b > mx ? b : mx;
+    }
+    if (mx) atomicMax(max_word(scale, d), mx);
+    if (bad && status) atomicOr(status, status_bit(RTF_ERR_VALUE));
+}
+
+__global__ __launch_bounds__(QT) void k_qapply(const float *__restrict__ v,
+                                               const int64_t *__restrict__ off, int32_t D,
+                                               int64_t n, const double *scale,
+                                               uint32_t *__restrict__ out) {
+    const int64_t i0 = ((int64_t)blockIdx.x * QT + threadIdx.x) * QI;
+    if (i0 >= n) return;
+    int32_t d = off ? find_segment(off, D, i0) : 0;
+    int64_t dend = off ? off[d + 1] : n;
+    float mx = __uint_as_float(*reinterpret_cast<const uint32_t *>(scale + d));
+    double s = mx > 0.0f ? 4294967295.0 / (double)mx : 0.0;
+    for (int e = 0; e < QI && i0 + e < n; ++e) {
+        const int64_t i = i0 + e;
+        while (i >= dend) {
+            ++d;
+            dend = off[d + 1];
+            mx = __uint_as_float(*reinterpret_cast<const uint32_t *>(scale + d));
+            s = mx > 0.0f ? 4294967295.0 / (double)mx : 0.0;
+        }
+        const float x = v[i];
+        uint32_t q = 0;
+        if (x > 0.0f && !isinf(x)) {
+            double y = rint((double)x * s);
+            y = y < 1.0 ? 1.0 : y;
+            y = y > 4294967295.0 ? 4294967295.0 : y;
+            q = (uint32_t)y;
+        }
+        out[i] = q;
+    }
+}
+
+__global__ void k_qfinal(double *scale, int32_t D) {
+    int32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= D) return;
+    const float mx = __uint_as_float(*reinterpret_cast<const uint32_t *>(scale + d));
+    scale[d] = mx > 0.0f ? 4294967295.0 / (double)mx : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_quantize(const float *v, const int64_t *elem_off, int32_t D, int64_t n_total,
+                           uint32_t *out, double *scale, uint32_t *status, hipStream_t st) {
+    const int db = (D + 255) / 256;
+    const int64_t nb = (n_total + (int64_t)QT * QI - 1) / ((int64_t)QT * QI);
+    hipLaunchKernelGGL(k_qinit, dim3(db), dim3(256), 0, st, scale, D);
+    hipLaunchKernelGGL(k_qmax, dim3((unsigned)nb), dim3(QT), 0, st, v, elem_off, D, n_total,
+                       scale, status);
+    hipLaunchKernelGGL(k_qapply, dim3((unsigned)nb), dim3(QT), 0, st, v, elem_off, D, n_total,
+                       scale, out);
+    hipLaunchKernelGGL(k_qfinal, dim3(db), dim3(256), 0, st, scale, D);
+    return hipGetLastError();
+}
+
+}  // namespace rtf

@@ -1,0 +1,236 @@
+// rtf_sample.hip -- Alg. 2 (guide-table lookup plus tree descent), the
+// continuous position of Sec. 5, the 2D component-by-component inversion of
+// Sec. 5, and two baselines with the identical mapping (Sec. 4): binary search
+// over all keys (Sec. 2.2) and the Cutpoint Method with bisection (Sec. 2.5).
+#include "rtf_internal.h"
+
+namespace rtf {
+
+namespace {
+
+__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
+    int32_t lo = 0, hi = D;
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline Node load_node(const Node *nodes, int64_t j) {
+    uint4 v = *reinterpret_cast<const uint4 *>(nodes + j);
+    Node r;
+    r.key = ((uint64_t)v.y << 32) | v.x;
+    r.c0 = (int32_t)v.z;
+    r.c1 = (int32_t)v.w;
+    return r;
+}
+
+// Alg. 2: g = floor(xi * m); follow the reference until it names a leaf.
+// A reference outside the forest, or a path longer than the forest has
+// nodes, can only come from a damaged workspace; it yields -1.
+__device__ inline int64_t descend(const Node *nodes, const int32_t *table, const Dist &P,
+                                  uint64_t u, int64_t n_total) {
+    int32_t j = table[P.co + (int64_t)mulhi64(u, (uint64_t)P.m)];
+    for (int64_t steps = 0; j >= 0; ++steps) {
+        if (j >= n_total || steps > n_total) return -1;
+        Node nd = load_node(nodes, j);
+        j = (u < nd.key) ? nd.c0 : nd.c1;
+    }
+    const int64_t i = (int64_t)(~j);
+    return (i >= P.eo && i < P.eo + P.n) ? i : -1;
+}
+
+// x = (i + ((t - C_i) + lo * 2^-64) / w_i) / n with t:lo = u * W, where
+// C_i = floor(U_i * W / 2^64) recovers the exact partial sum from the key.
+__device__ inline double position(const Node *nodes, const Dist &P, int64_t i, uint64_t u) {
+    const uint64_t W = P.W;
+    const uint64_t Ci = mulhi64(nodes[i].key, W);
+    uint64_t Cn = W;
+    if (i + 1 < P.eo + P.n) {
+        uint64_t k1 = nodes[i + 1].key;
+        if (k1 != ~0ull) Cn = mulhi64(k1, W);
+    }
+    const uint64_t t = mulhi64(u, W);
+    const uint64_t lo = u * W;
+    const double frac = ((double)(t - Ci) + ldexp((double)lo, -64)) / (double)(Cn - Ci);
+    return ((double)(i - P.eo) + frac) / (double)P.n;
+}
+
+template <bool BATCHED, bool WANT_X>
+__global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
+                                                const int32_t *__restrict__ table,
+                                                const Dist *__restrict__ dists,
+                                                const int64_t *__restrict__ sample_off,
+                                                int32_t D, int64_t n_total,
+                                                const uint64_t *__restrict__ u, int64_t S,
+                                                int32_t *__restrict__ idx,
+                                                double *__restrict__ x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
+        const int32_t d = BATCHED ? find_segment(sample_off, D, s) : 0;
+        const Dist &P = dists[d];
+        const uint64_t us = __builtin_nontemporal_load(u + s);
+        const int64_t i = (P.flags & DIST_ZERO) ? -1 : descend(nodes, table, P, us, n_total);
+        if (i < 0) {
+            idx[s] = -1;
+            if (WANT_X) x[s] = __builtin_nan("");
+            continue;
+        }
+        __builtin_nontemporal_store((int32_t)(i - P.eo), idx + s);
+        if (WANT_X) __builtin_nontemporal_store(position(nodes, P, i, us), x + s);
+    }
+}
+
+template <bool WANT_X>
+__global__ __launch_bounds__(256) void k_sample_2d(const Node *__restrict__ nodes,
+                                                   const int32_t *__restrict__ table,
+                                                   const Dist *__restrict__ dists, int32_t D,
+                                                   int64_t n_total,
+                                                   const uint64_t *__restrict__ u2, int64_t S,
+                                                   int32_t *__restrict__ rc,
+                                                   double *__restrict__ xy) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const Dist &M = dists[0];
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
+        const uint64_t ur = u2[2 * s], uc = u2[2 * s + 1];
+        const int64_t ig = (M.flags & DIST_ZERO) ? -1 : descend(nodes, table, M, ur, n_total);
+        const int64_t r = ig - M.eo;
+        // the marginal must have one weight per row distribution 1..D-1
+        if (ig < 0 || 1 + r >= D) {
+            rc[2 * s] = rc[2 * s + 1] = -1;
+            if (WANT_X) xy[2 * s] = xy[2 * s + 1] = __builtin_nan("");
+            continue;
+        }
+        rc[2 * s] = (int32_t)r;
+        if (WANT_X) xy[2 * s] = position(nodes, M, ig, ur);
+        const Dist &R = dists[1 + r];
+        const int64_t jg = (R.flags & DIST_ZERO) ? -1 : descend(nodes, table, R, uc, n_total);
+        if (jg < 0) {
+            rc[2 * s + 1] = -1;
+            if (WANT_X) xy[2 * s + 1] = __builtin_nan("");
+            continue;
+        }
+        rc[2 * s + 1] = (int32_t)(jg - R.eo);
+        if (WANT_X) xy[2 * s + 1] = position(nodes, R, jg, uc);
+    }
+}
+
+// last leaf x in [lo, hi] of the distribution with key_x <= u; keys of leaves
+// past the last positive weight are all-ones and never qualify
+__device__ inline int64_t bisect(const Node *nodes, int64_t lo, int64_t hi, uint64_t u) {
+    // invariant: key[lo] <= u (lo qualifies), hi + 1 does not
+    int64_t a = lo, b = hi + 1;
+    while (b - a > 1) {
+        int64_t mid = a + (b - a) / 2;
+        uint64_t k = nodes[mid].key;
+        if (k != ~0ull && k <= u) a = mid;
+        else b = mid;
+    }
+    return a;
+}
+
+template <bool CUTPOINT, bool WANT_X>
+__global__ __launch_bounds__(256) void k_sample_bsearch(const Node *__restrict__ nodes,
+                                                        const int32_t *__restrict__ table,
+                                                        const Dist *__restrict__ dists,
+                                                        const uint64_t *__restrict__ u,
+                                                        int64_t S, int32_t *__restrict__ idx,
+                                                        double *__restrict__ x) {
+    const Dist &P = dists[0];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
+        const uint64_t us = u[s];
+        if (P.flags & DIST_ZERO) {
+            idx[s] = -1;
+            if (WANT_X) x[s] = __builtin_nan("");
+            continue;
+        }
+        const int64_t first = P.eo, last = P.eo + P.n - 1;
+        int64_t lo = first, hi = last;
+        if (CUTPOINT) {
+            // the cell's first overlapping interval bounds the search from
+            // below, the next cell's first overlapping interval from above
+            const int64_t g = (int64_t)mulhi64(us, (uint64_t)P.m);
+            const int32_t r0 = table[P.co + g];
+            if (r0 < 0) {
+                lo = hi = ~r0;
+            } else {
+                lo = (r0 > P.eo) ? r0 - 1 : r0;
+                if (g + 1 < P.m) {
+                    const int32_t r1 = table[P.co + g + 1];
+                    hi = (r1 < 0) ? ~r1 : r1;
+                }
+            }
+        }
+        lo = lo < first ? first : (lo > last ? last : lo);
+        hi = hi < lo ? lo : (hi > last ? last : hi);
+        const int64_t i = (lo == hi) ? lo : bisect(nodes, lo, hi, us);
+        idx[s] = (int32_t)(i - P.eo);
+        if (WANT_X) x[s] = position(nodes, P, i, us);
+    }
+}
+
+inline int grid_for(int64_t S) {
+    int64_t b = (S + 255) / 256;
+    const int64_t cap = 256 * 64;  // 256 CUs x 64 blocks in flight at most
+    return (int)(b < cap ? b : cap);
+}
+
+}  // namespace
+
+hipError_t launch_sample(const Node *nodes, const int32_t *table, const Dist *dists,
+                         const int64_t *sample_off, int32_t D, int64_t n_total,
+                         const uint64_t *u, int64_t S, int32_t *idx, double *x,
+                         hipStream_t st) {
+    const dim3 g(grid_for(S)), b(256);
+    const bool batched = sample_off != nullptr;
+    if (batched && x)
+        hipLaunchKernelGGL((k_sample<true, true>), g, b, 0, st, nodes, table, dists, sample_off,
+                           D, n_total, u, S, idx, x);
+    else if (batched)
+        hipLaunchKernelGGL((k_sample<true, false>), g, b, 0, st, nodes, table, dists,
+                           sample_off, D, n_total, u, S, idx, x);
+    else if (x)
+        hipLaunchKernelGGL((k_sample<false, true>), g, b, 0, st, nodes, table, dists,
+                           sample_off, D, n_total, u, S, idx, x);
+    else
+        hipLaunchKernelGGL((k_sample<false, false>), g, b, 0, st, nodes, table, dists,
+                           sample_off, D, n_total, u, S, idx, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_2d(const Node *nodes, const int32_t *table, const Dist *dists,
+                            int32_t D, int64_t n_total, const uint64_t *u2, int64_t S,
+                            int32_t *rc, double *xy, hipStream_t st) {
+    const dim3 g(grid_for(S)), b(256);
+    if (xy)
+        hipLaunchKernelGGL((k_sample_2d<true>), g, b, 0, st, nodes, table, dists, D, n_total, u2,
+                           S, rc, xy);
+    else
+        hipLaunchKernelGGL((k_sample_2d<false>), g, b, 0, st, nodes, table, dists, D, n_total,
+                           u2, S, rc, xy);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_bsearch(const Node *nodes, const int32_t *table, const Dist *dists,
+                                 bool cutpoint, const uint64_t *u, int64_t S, int32_t *idx,
+                                 double *x, hipStream_t st) {
+    const dim3 g(grid_for(S)), b(256);
+    if (cutpoint && x)
+        hipLaunchKernelGGL((k_sample_bsearch<true, true>), g, b, 0, st, nodes, table, dists, u,
+                           S, idx, x);
+    else if (cutpoint)
+        hipLaunchKernelGGL((k_sample_bsearch<true, false>), g, b, 0, st, nodes, table, dists, u,
+                           S, idx, x);
+    else if (x)
+        hipLaunchKernelGGL((k_sample_bsearch<false, true>), g, b, 0, st, nodes, table, dists, u,
+                           S, idx, x);
+    else
+        hipLaunchKernelGGL((k_sample_bsearch<false, false>), g, b, 0, st, nodes, table, dists,
+                           u, S, idx, x);
+    return hipGetLastError();
+}
+
+}  // namespace rtf

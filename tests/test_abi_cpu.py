@@ -1,0 +1,95 @@
+"""CPU tests of the HIP library's host side: it loads, exports every symbol the
+header declares, sizes workspaces, rejects bad arguments before any launch,
+and its exact fixed-point helpers agree with 128-bit integer arithmetic."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtforest.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1901_05423_amd as rtf
+    if not os.path.exists(rtf.LIB_PATH):
+        from paper_1901_05423_amd.build import build_library
+        build_library()
+    return rtf.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("rtf_build", "rtf_build_batched", "rtf_sample", "rtf_sample_batched",
+                 "rtf_sample_2d", "rtf_backward", "rtf_quantize_f32", "rtf_check",
+                 "rtf_forest_export", "rtf_workspace_bytes", "rtf_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    nm = subprocess.run(["nm", "-D", "--defined-only", L._name], capture_output=True,
+                        text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (rtf_\w+)", nm))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    import paper_1901_05423_amd as rtf
+    assert set(declared_functions()) == set(rtf.SIGNATURES)
+
+
+def test_workspace_sizes(L):
+    a = L.rtf_workspace_bytes(1 << 24, 1 << 24)
+    assert a >= 16 * (1 << 24) + 4 * (1 << 24)
+    assert a % 256 == 0
+    assert L.rtf_workspace_bytes(0, 5) == 0
+    assert L.rtf_workspace_bytes(5, 0) == 0
+    assert L.rtf_workspace_bytes(1 << 31, 5) == 0
+    assert L.rtf_workspace_bytes_batched(3, 2, 10) == 0  # fewer weights than distributions
+    assert L.rtf_workspace_bytes_batched(3, 30, 30) > 0
+    assert L.rtf_backward_workspace_bytes(2, 100) >= 2 * 8 * 100
+
+
+def test_argument_errors_before_launch(L):
+    import paper_1901_05423_amd as rtf
+    desc = rtf.rtf_forest()
+    P = ctypes.c_void_p
+    fake = P(0x100000)  # never dereferenced: every call below fails validation
+    r = L.rtf_build(None, 10, 10, fake, 1 << 20, None, ctypes.byref(desc))
+    assert r == rtf.RTF_ERR_INVALID_ARG
+    r = L.rtf_build(fake, 0, 10, fake, 1 << 20, None, ctypes.byref(desc))
+    assert r == rtf.RTF_ERR_INVALID_ARG
+    r = L.rtf_build(fake, 10, 10, P(0x100001), 1 << 20, None, ctypes.byref(desc))
+    assert r == rtf.RTF_ERR_INVALID_ARG  # misaligned workspace
+    r = L.rtf_build(fake, 1 << 31, 10, fake, 1 << 40, None, ctypes.byref(desc))
+    assert r == rtf.RTF_ERR_SIZE
+    r = L.rtf_build(fake, 1000, 1000, fake, 64, None, ctypes.byref(desc))
+    assert r == rtf.RTF_ERR_WORKSPACE
+    r = L.rtf_sample(None, fake, 10, fake, None, None)
+    assert r == rtf.RTF_ERR_INVALID_ARG
+    r = L.rtf_sample(ctypes.byref(desc), fake, 10, fake, None, None)  # empty descriptor
+    assert r == rtf.RTF_ERR_INVALID_ARG
+    r = L.rtf_quantize_f32(None, None, 1, 10, fake, fake, None, None)
+    assert r == rtf.RTF_ERR_INVALID_ARG
+    for c in range(7):
+        assert L.rtf_status_string(c).decode().startswith("RTF_")
+
+
+def test_fixed_point_helpers_exact(tmp_path):
+    src = os.path.join(ROOT, "tests", "native", "fixed_point_check.hip")
+    exe = str(tmp_path / "fixed_point_check")
+    subprocess.run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O2", "-std=c++17",
+                    "-I", os.path.join(ROOT, "include"), "-o", exe, src], check=True,
+                   capture_output=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0 and out.stdout.strip().endswith("OK"), out.stdout

@@ -1,0 +1,217 @@
+"""GPU parity: one distribution, built and sampled through the C ABI, against
+the CPU oracle.  Forests, guide tables and indices bit-exact; x within 1e-12
+(the method's bar is 1e-6)."""
+import numpy as np
+import pytest
+
+from gpu_util import (X_TOL, assert_forest, assert_samples, critical_u, note, random_weights,
+                      to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rtf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1901_05423_amd as rtf
+    rtf.lib()
+    return rtf
+
+
+def build_and_compare(rtf, orc, w, m, S_extra=20000, seed=0, baselines=True):
+    rng = np.random.default_rng(seed)
+    f = rtf.build(to_dev(w), m)
+    f.check()
+    ref = orc.forest(w, m=m)
+    assert_forest(f, ref, f"n={w.size} m={m}")
+    u = critical_u(ref.key, int(ref.W[0]), m, extra=S_extra, rng=rng)
+    ud = to_dev(u)
+    i_ref, x_ref = orc.search(w, u)
+    idx, x = rtf.sample(f, ud)
+    assert_samples(idx.cpu().numpy(), x.cpu().numpy(), i_ref, x_ref)
+    idx_only, none = rtf.sample(f, ud, want_x=False)
+    assert none is None and np.array_equal(idx_only.cpu().numpy(), i_ref)
+    if baselines:
+        for fn in (rtf.sample_bsearch, rtf.sample_cutpoint_bsearch):
+            bi, bx = fn(f, ud)
+            assert_samples(bi.cpu().numpy(), bx.cpu().numpy(), i_ref, x_ref)
+    return f
+
+
+def test_c1_uniform_1k(rtf, orc):
+    """n=1024 uniform(0,1] weights, quantised on the GPU, m=1024, 2^16 uniforms."""
+    import torch
+    from paper_1901_05423_amd import workloads as wl
+    note("C1 n=1024 m=1024 S=65536")
+    r = wl.rng(wl.C1_UNIFORM_1K)
+    v = wl.weights_uniform(r, 1024)
+    u = wl.uniforms(r, 1 << 16)
+    q_ref, s_ref = orc.quantize(v)
+    q, s = rtf.quantize(to_dev(v))
+    assert np.array_equal(q.cpu().numpy(), q_ref)
+    assert s.cpu().numpy()[0] == s_ref[0]
+    f = rtf.build(q, 1024)
+    assert_forest(f, orc.forest(q_ref, m=1024))
+    idx, x = rtf.sample(f, to_dev(u))
+    i_ref, x_ref = orc.search(q_ref, u)
+    assert_samples(idx.cpu().numpy(), x.cpu().numpy(), i_ref, x_ref)
+    torch.cuda.synchronize()
+
+
+CASES = [
+    # (n, m, zero_frac, skew, trailing_zeros)
+    (1, 1, 0.0, False, 0),
+    (1, 5, 0.0, False, 0),
+    (2, 1, 0.0, False, 0),
+    (3, 2, 0.5, True, 0),
+    (17, 17, 0.0, False, 3),
+    (100, 1, 0.0, True, 0),
+    (100, 300, 0.3, False, 0),
+    (4095, 4095, 0.0, False, 0),
+    (4096, 4096, 0.0, True, 0),
+    (4097, 4097, 0.2, False, 5),
+    (3 * 4096 + 5, 1, 0.0, False, 0),
+    (3 * 4096 + 5, 7, 0.0, True, 0),
+    (3 * 4096 + 5, 3 * (3 * 4096 + 5), 0.1, False, 0),
+    (70001, 70001, 0.0, False, 0),
+    (70001, 65536, 0.9, True, 40),
+    (70001, 100, 0.5, False, 0),
+    (200003, 200003, 0.0, True, 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "n%d_m%d_z%g_s%d_t%d" % (
+    c[0], c[1], c[2], c[3], c[4]))
+def test_forest_and_samples(rtf, orc, case):
+    n, m, zf, skew, trail = case
+    note(f"single n={n} m={m} zeros={zf} skew={skew} trailing={trail}")
+    rng = np.random.default_rng(n * 7919 + m)
+    w = random_weights(rng, n, zero_frac=zf, skew=skew)
+    if trail:
+        w[-trail:] = 0
+        if w.sum() == 0:
+            w[0] = 5
+    build_and_compare(rtf, orc, w, m, seed=n + m)
+
+
+def test_leading_zero_runs_and_duplicates(rtf, orc):
+    """Long runs of zero weights make runs of equal keys (ties in the levels)."""
+    note("zero runs n=50000")
+    rng = np.random.default_rng(99)
+    n = 50000
+    w = random_weights(rng, n)
+    w[:3000] = 0
+    w[10000:14000] = 0
+    w[20000:20100] = 0
+    w[-5000:] = 0
+    for m in (1, 1000, n):
+        build_and_compare(rtf, orc, w, m, seed=m)
+
+
+def test_single_heavy_interval(rtf, orc):
+    """One interval covering most cells: long guide-table runs."""
+    note("heavy interval n=20000")
+    rng = np.random.default_rng(5)
+    w = random_weights(rng, 20000, skew=False) // 1000
+    w[1234] = 4000000000
+    w[17] = 4000000000
+    build_and_compare(rtf, orc, w, 20000)
+    build_and_compare(rtf, orc, w, 3 * 20000 + 1)
+
+
+def test_zero_total_is_reported(rtf, orc):
+    note("all-zero weights")
+    import paper_1901_05423_amd as rtfm
+    w = np.zeros(100, np.uint32)
+    f = rtf.build(to_dev(w), 10)
+    with pytest.raises(rtfm.RtfError) as e:
+        f.check()
+    assert e.value.code == rtfm.RTF_ERR_ZERO_TOTAL
+    idx, x = rtf.sample(f, to_dev(np.array([0, 5, 2 ** 63], np.uint64)))
+    assert (idx.cpu().numpy() == -1).all() and np.isnan(x.cpu().numpy()).all()
+
+
+def test_quantize_value_errors(rtf, orc):
+    note("quantize negative")
+    import torch
+    import paper_1901_05423_amd as rtfm
+    st = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    v = np.array([1.0, 2.0, -1.0, 0.0], np.float32)
+    q, _ = rtf.quantize(to_dev(v), status=st)
+    assert int(st.item()) & (1 << rtfm.RTF_ERR_VALUE)
+    assert q.cpu().numpy()[2] == 0
+
+
+def test_quantize_parity_batched(rtf, orc):
+    note("quantize batched")
+    rng = np.random.default_rng(3)
+    sizes = [1, 4096, 17, 5000, 3, 40000]
+    v = np.concatenate([rng.random(s).astype(np.float32) * 10 ** rng.uniform(-3, 3)
+                        for s in sizes])
+    v[::31] = 0
+    eo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    q_ref, s_ref = orc.quantize(v, eo)
+    q, s = rtf.quantize(to_dev(v), to_dev(eo))
+    assert np.array_equal(q.cpu().numpy(), q_ref)
+    assert np.array_equal(s.cpu().numpy(), s_ref)
+
+
+def test_deterministic_rebuild(rtf, orc):
+    note("determinism n=300000")
+    rng = np.random.default_rng(11)
+    w = random_weights(rng, 300000, zero_frac=0.05, skew=True)
+    wd = to_dev(w)
+    f1 = rtf.build(wd, 300000)
+    a = f1.export()
+    for _ in range(5):
+        f2 = rtf.build(wd, 300000)
+        b = f2.export()
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_c2_zipf_2e20_full_forest(rtf, orc):
+    """n=2^20, p_i ~ (i+1)^-1.1 permuted, m=n: forest bit-exact, 2^22 uniforms."""
+    import torch
+    from paper_1901_05423_amd import workloads as wl
+    note("C2 zipf n=2^20 m=2^20")
+    r = wl.rng(wl.C2_ZIPF_1M)
+    n = 1 << 20
+    v = wl.weights_zipf(r, n)
+    u = wl.uniforms(r, 1 << 22)
+    q_ref, _ = orc.quantize(v)
+    q, _ = rtf.quantize(to_dev(v))
+    assert np.array_equal(q.cpu().numpy(), q_ref)
+    f = rtf.build(q, n)
+    assert_forest(f, orc.forest(q_ref, m=n), "C2")
+    idx, x = rtf.sample(f, to_dev(u))
+    i_ref, x_ref = orc.search(q_ref, u)
+    assert_samples(idx.cpu().numpy(), x.cpu().numpy(), i_ref, x_ref)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kind", ["uniform", "zipf"])
+def test_h24_full_size(rtf, orc, kind):
+    """n=2^24, m=n (the benchmark's configuration): forest bit-exact against
+    the oracle's, 2^22 of the benchmark's uniforms checked one by one."""
+    import torch
+    from paper_1901_05423_amd import workloads as wl
+    note(f"H24 {kind} n=2^24 m=2^24")
+    n = 1 << 24
+    r = wl.rng(wl.H24_UNIFORM if kind == "uniform" else wl.H24_ZIPF)
+    v = wl.weights_uniform(r, n) if kind == "uniform" else wl.weights_zipf(r, n)
+    u = wl.uniforms(r, 1 << 22)
+    q_ref, _ = orc.quantize(v)
+    q, _ = rtf.quantize(to_dev(v))
+    assert np.array_equal(q.cpu().numpy(), q_ref)
+    note("H24 quantised weights match; building")
+    f = rtf.build(q, n)
+    ref = orc.forest(q_ref, m=n)
+    note("H24 oracle forest done; comparing")
+    assert_forest(f, ref, "H24")
+    note("H24 forest matches; sampling")
+    idx, x = rtf.sample(f, to_dev(u))
+    i_ref, x_ref = orc.search(q_ref, u)
+    assert_samples(idx.cpu().numpy(), x.cpu().numpy(), i_ref, x_ref)
+    torch.cuda.synchronize()
