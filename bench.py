@@ -136,6 +136,12 @@ def main():
         rtf.sample(f, u, out=(idx, x))
         out["bsearch_samples_s"] = S / (t_bs * 1e-3)
         out["cutpoint_bsearch_samples_s"] = S / (t_cb * 1e-3)
+    if args.profile:
+        # calibration for the HBM byte counters: a plain copy of known size
+        src = torch.empty(1 << 28, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
     torch.cuda.synchronize()
 
     # algorithmic bytes per sample of the sampling kernel: stream u, idx, x;

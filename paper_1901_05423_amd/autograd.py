@@ -19,8 +19,7 @@ class RTFSample(torch.autograd.Function):
     u           uint64[S] uniforms; sample_off int64[D+1] splits them by
                 distribution; elem_off int64[D+1] splits v
     cell_ratio  guide cells per weight (m_d = round(ratio * n_d), at least 1)
-    Returns x float64[S]; the sampled indices are kept in ``ctx`` and exposed
-    through the ``last_indices`` attribute of the returned tensor.
+    Returns x float64[S].
     """
 
     @staticmethod
@@ -31,7 +30,6 @@ class RTFSample(torch.autograd.Function):
         ctx.forest = f
         ctx.save_for_backward(u, idx, scale, sample_off)
         ctx.v_dtype = v.dtype
-        x.last_indices = idx
         return x
 
     @staticmethod

@@ -37,12 +37,22 @@ __global__ void k_qinit(double *scale, int32_t D) {
     if (d < D) scale[d] = 0.0;
 }
 
+// Blocks whose elements all lie in one distribution reduce in LDS and issue
+// one atomic; blocks that straddle distributions flush per lane and segment.
 __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
                                              const int64_t *__restrict__ off, int32_t D,
                                              int64_t n, double *scale, uint32_t *status) {
-    const int64_t i0 = ((int64_t)blockIdx.x * QT + threadIdx.x) * QI;
-    if (i0 >= n) return;
-    int32_t d = off ? find_segment(off, D, i0) : 0;
+    __shared__ uint32_t s_max[QT / 64];
+    __shared__ int s_bad;
+    const int64_t b0 = (int64_t)blockIdx.x * QT * QI;
+    const int64_t b1 = b0 + (int64_t)QT * QI < n ? b0 + (int64_t)QT * QI : n;
+    const int32_t dfirst = off ? find_segment(off, D, b0) : 0;
+    const bool one = !off || off[dfirst + 1] >= b1;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    const int64_t i0 = b0 + (int64_t)threadIdx.x * QI;
+    int32_t d = dfirst;
+    if (!one && i0 < n) d = find_segment(off, D, i0);
     int64_t dend = off ? off[d + 1] : n;
     uint32_t mx = 0;
     bool bad = false;
@@ -62,8 +72,26 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
         const uint32_t b = __float_as_uint(x);
         mx = b > mx ? b : mx;
     }
-    if (mx) atomicMax(max_word(scale, d), mx);
-    if (bad && status) atomicOr(status, status_bit(RTF_ERR_VALUE));
+    if (bad) s_bad = 1;
+    if (one) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t y = __shfl_down(mx, o, 64);
+            mx = y > mx ? y : mx;
+        }
+        if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t m = 0;
+            for (int w = 0; w < QT / 64; ++w) m = s_max[w] > m ? s_max[w] : m;
+            if (m) atomicMax(max_word(scale, dfirst), m);
+            if (s_bad && status) atomicOr(status, status_bit(RTF_ERR_VALUE));
+        }
+    } else {
+        if (mx) atomicMax(max_word(scale, d), mx);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_bad && status) atomicOr(status, status_bit(RTF_ERR_VALUE));
+    }
 }
 
 __global__ __launch_bounds__(QT) void k_qapply(const float *__restrict__ v,

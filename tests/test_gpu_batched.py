@@ -1,0 +1,261 @@
+"""GPU parity for many distributions at once (Sec. 5): batched builds and
+samples, the two-dimensional inversion, and the adjoint of x."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_forest, assert_samples, note, random_weights, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rtf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1901_05423_amd as rtf
+    rtf.lib()
+    return rtf
+
+
+def offsets(sizes):
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+
+def check_batched(rtf, orc, ws, cells, sample_counts, seed):
+    rng = np.random.default_rng(seed)
+    w = np.concatenate(ws)
+    eo = offsets([a.size for a in ws])
+    co = offsets(cells)
+    f = rtf.build_batched(to_dev(w), to_dev(eo), to_dev(co))
+    f.check()
+    ref = orc.forest(w, elem_off=eo, cell_off=co)
+    assert_forest(f, ref, f"D={len(ws)}")
+    so = offsets(sample_counts)
+    u = rng.integers(0, 2 ** 64, int(so[-1]), dtype=np.uint64)
+    idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
+    idx, x = idx.cpu().numpy(), x.cpu().numpy()
+    for d, wd in enumerate(ws):
+        a, b = so[d], so[d + 1]
+        if a == b:
+            continue
+        i_ref, x_ref = orc.search(wd, u[a:b])
+        assert_samples(idx[a:b], x[a:b], i_ref, x_ref)
+    return f
+
+
+def test_batched_random_sizes(rtf, orc):
+    note("batched D=60 random sizes")
+    rng = np.random.default_rng(21)
+    sizes = rng.integers(1, 6000, 60)
+    sizes[:5] = [1, 1, 2, 4096, 4097]
+    ws = [random_weights(rng, int(s), zero_frac=[0, 0.3, 0.95][k % 3], skew=k % 2 == 0)
+          for k, s in enumerate(sizes)]
+    for k in (7, 19):
+        ws[k][-3:] = 0  # trailing zeros inside the batch
+        if ws[k].sum() == 0:
+            ws[k][0] = 1
+    cells = [max(1, int(s * r)) for s, r in zip(sizes, rng.uniform(0.01, 3, 60))]
+    counts = rng.integers(0, 3000, 60)
+    counts[3] = 0
+    counts[10:13] = 0
+    check_batched(rtf, orc, ws, cells, counts, 1)
+
+
+def test_batched_tile_straddling(rtf, orc):
+    """Distributions that start and end at and around the 4096-element tiles."""
+    note("batched straddling tiles")
+    rng = np.random.default_rng(22)
+    sizes = [4095, 1, 4096, 2, 8190, 1, 1, 1, 12289, 3, 4096, 4096]
+    ws = [random_weights(rng, s, zero_frac=0.1) for s in sizes]
+    cells = [s for s in sizes]
+    cells[4] = 1
+    cells[8] = 50000
+    check_batched(rtf, orc, ws, cells, [500] * len(sizes), 2)
+
+
+def test_batched_zero_distribution(rtf, orc):
+    note("batched with an all-zero distribution")
+    import paper_1901_05423_amd as rtfm
+    rng = np.random.default_rng(23)
+    ws = [random_weights(rng, 100), np.zeros(50, np.uint32), random_weights(rng, 70)]
+    w = np.concatenate(ws)
+    eo, co = offsets([100, 50, 70]), offsets([100, 50, 70])
+    f = rtf.build_batched(to_dev(w), to_dev(eo), to_dev(co))
+    with pytest.raises(rtfm.RtfError):
+        f.check()
+    so = offsets([10, 10, 10])
+    u = rng.integers(0, 2 ** 64, 30, dtype=np.uint64)
+    idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
+    idx = idx.cpu().numpy()
+    assert (idx[10:20] == -1).all() and np.isnan(x.cpu().numpy()[10:20]).all()
+    for d in (0, 2):
+        i_ref, _ = orc.search(ws[d], u[10 * d:10 * d + 10])
+        assert np.array_equal(idx[10 * d:10 * d + 10], i_ref)
+
+
+def test_c4_batched_uneven_full(rtf, orc):
+    """10,000 distributions, sizes log-uniform in [16, 65536], uniform or
+    Pareto(1.2) weights, ceil(64 n_d / 1000) uniforms each."""
+    import torch
+    from paper_1901_05423_amd import workloads as wl
+    note("C4 batched D=10000")
+    r = wl.rng(wl.C4_BATCHED)
+    v, eo, so = wl.batched_uneven(r)
+    u = wl.uniforms(r, int(so[-1]))
+    q_ref, s_ref = orc.quantize(v, eo)
+    q, s = rtf.quantize(to_dev(v), to_dev(eo))
+    assert np.array_equal(q.cpu().numpy(), q_ref)
+    assert np.array_equal(s.cpu().numpy(), s_ref)
+    note(f"C4 n_total={eo[-1]} S={so[-1]}: building")
+    eod = to_dev(eo)
+    f = rtf.build_batched(q, eod, rtf.cells_like(eod))
+    f.check()
+    ref = orc.forest(q_ref, elem_off=eo, cell_off=eo)
+    note("C4 oracle forest done")
+    assert_forest(f, ref, "C4")
+    idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
+    idx, x = idx.cpu().numpy(), x.cpu().numpy()
+    note("C4 comparing samples")
+    i_ref = np.empty_like(idx)
+    x_ref = np.empty_like(x)
+    for d in range(eo.size - 1):
+        a, b = so[d], so[d + 1]
+        i_ref[a:b], x_ref[a:b] = orc.search(q_ref[eo[d]:eo[d + 1]], u[a:b])
+    assert_samples(idx, x, i_ref, x_ref)
+    torch.cuda.synchronize()
+
+
+def quantised_map(orc, img, marginal):
+    R, C = img.shape
+    v = np.concatenate([marginal, img.ravel()])
+    eo = np.concatenate([[0, R], R + C * np.arange(1, R + 1)]).astype(np.int64)
+    q, _ = orc.quantize(v, eo)
+    return v, q, eo
+
+
+def check_2d(rtf, orc, img, marginal, pairs, seed, zero_rows=False):
+    rng = np.random.default_rng(seed)
+    R, C = img.shape
+    v, q_ref, eo = quantised_map(orc, img, marginal)
+    q, _ = rtf.quantize(to_dev(v), to_dev(eo))
+    assert np.array_equal(q.cpu().numpy(), q_ref)
+    eod = to_dev(eo)
+    f = rtf.build_batched(q, eod, rtf.cells_like(eod))
+    if zero_rows:  # an all-zero row is a distribution without mass
+        import paper_1901_05423_amd as rtfm
+        with pytest.raises(rtfm.RtfError):
+            f.check()
+    else:
+        f.check()
+    u2 = rng.integers(0, 2 ** 64, 2 * pairs, dtype=np.uint64)
+    rc, xy = rtf.sample_2d(f, to_dev(u2))
+    rc, xy = rc.cpu().numpy(), xy.cpu().numpy()
+    r_ref, y_ref = orc.search(q_ref[:R], u2[0::2])
+    assert_samples(rc[:, 0], xy[:, 0], r_ref, y_ref)
+    c_ref = np.empty(pairs, np.int32)
+    x_ref = np.empty(pairs)
+    order = np.argsort(r_ref, kind="stable")
+    rows, starts = np.unique(r_ref[order], return_index=True)
+    bounds = list(starts) + [pairs]
+    for k, row in enumerate(rows):
+        sel = order[bounds[k]:bounds[k + 1]]
+        lo = R + int(row) * C
+        c_ref[sel], x_ref[sel] = orc.search(q_ref[lo:lo + C], u2[1::2][sel])
+    assert_samples(rc[:, 1], xy[:, 1], c_ref, x_ref)
+    return f, q_ref, eo
+
+
+def test_2d_small_map(rtf, orc):
+    note("2D 96x130")
+    from paper_1901_05423_amd import workloads as wl
+    img, marg = wl.map_2d(np.random.default_rng(31), rows=96, cols=130, spots=3)
+    img[5] = 0  # an empty row is never picked
+    marg = img.astype(np.float64).sum(axis=1).astype(np.float32)
+    check_2d(rtf, orc, img, marg, 200000, 3, zero_rows=True)
+
+
+def test_c3_2d_full_map(rtf, orc):
+    """4096 x 4096 log-normal(0, 1.5) map with 8 hot spots: forest of the
+    marginal plus 4096 rows bit-exact, 2^20 pairs checked."""
+    from paper_1901_05423_amd import workloads as wl
+    note("C3 2D 4096x4096")
+    img, marg = wl.map_2d(wl.rng(wl.C3_MAP_2D))
+    f, q_ref, eo = check_2d(rtf, orc, img, marg, 1 << 20, 4)
+    note("C3 samples match; comparing forest")
+    assert_forest(f, orc.forest(q_ref, elem_off=eo, cell_off=eo), "C3")
+
+
+def check_grad(rtf, orc, D, n, per, check_dists, seed):
+    import torch
+    import paper_1901_05423_amd as rtfm
+    from paper_1901_05423_amd import workloads as wl
+    r = wl.rng(seed)
+    z_h = wl.logits(r, D, n)
+    u_h = wl.uniforms(r, D * per)
+    z = torch.from_numpy(z_h).to("cuda:0").requires_grad_(True)
+    v = torch.nn.functional.softplus(z).reshape(-1)
+    eo = to_dev(np.arange(D + 1, dtype=np.int64) * n)
+    so = to_dev(np.arange(D + 1, dtype=np.int64) * per)
+    u = to_dev(u_h)
+    x = rtfm.RTFSample.apply(v, u, eo, so, 1.0)
+    L = torch.sin(7.0 * x).sum()
+    L.backward()
+    gz = z.grad.detach().double().cpu().numpy()
+    x_h = x.detach().cpu().numpy()
+    v_h = v.detach().cpu().numpy()
+    sig = 1.0 / (1.0 + np.exp(-z_h.astype(np.float64)))
+    for d in check_dists:
+        q, s = orc.quantize(v_h[d * n:(d + 1) * n])
+        uu = u_h[d * per:(d + 1) * per]
+        i_ref, x_ref = orc.search(q, uu)
+        assert np.abs(x_h[d * per:(d + 1) * per] - x_ref).max() <= 1e-12
+        g = 7.0 * np.cos(7.0 * x_ref)
+        ref = orc.grad(q, s[0], uu, g) * sig[d]
+        got = gz[d]
+        err = np.abs(got - ref)
+        assert err.max() <= 1e-4 * np.abs(ref).max(), (d, err.max(), np.abs(ref).max())
+        assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+def test_grad_small(rtf, orc):
+    note("grad D=6 n=4096 2^16 each")
+    check_grad(rtf, orc, 6, 4096, 1 << 16, range(6), 105)
+
+
+def test_grad_uneven_raw(rtf, orc):
+    """rtf_backward directly on an uneven batch, against the oracle."""
+    note("grad uneven raw")
+    import torch
+    rng = np.random.default_rng(41)
+    sizes = [1, 300, 4096, 5000, 17]
+    vs = [(0.01 + rng.random(s)).astype(np.float32) for s in sizes]
+    vs[2][100] = 0
+    v = np.concatenate(vs)
+    eo = offsets(sizes)
+    counts = [100, 0, 30000, 20000, 5]
+    so = offsets(counts)
+    u = rng.integers(0, 2 ** 64, int(so[-1]), dtype=np.uint64)
+    g = rng.standard_normal(int(so[-1]))
+    q, s = rtf.quantize(to_dev(v), to_dev(eo))
+    eod = to_dev(eo)
+    f = rtf.build_batched(q, eod, eod)
+    ud, sod = to_dev(u), to_dev(so)
+    idx, _ = rtf.sample_batched(f, sod, ud)
+    gw = rtf.backward(f, ud, idx, to_dev(g), s, sample_off=sod).cpu().numpy()
+    q_h, s_h = q.cpu().numpy(), s.cpu().numpy()
+    for d in range(len(sizes)):
+        a, b = eo[d], eo[d + 1]
+        ref = orc.grad(q_h[a:b], s_h[d], u[so[d]:so[d + 1]], g[so[d]:so[d + 1]])
+        got = gw[a:b]
+        # a one-weight distribution has gradient exactly 0 (x = xi for any
+        # weight); there the bar is absolute
+        scale = max(np.abs(ref).max(), 1.0)
+        assert np.abs(got - ref).max() <= 1e-9 * scale, d
+    torch.cuda.synchronize()
+
+
+def test_c5_grad_full(rtf, orc):
+    """256 distributions of 4096 softplus(N(0,1)) weights, 2^20 uniforms each,
+    L = sum sin(7x): dL/dlogits of 4 distributions checked against the oracle."""
+    note("C5 grad D=256 n=4096 2^20 each")
+    check_grad(rtf, orc, 256, 4096, 1 << 20, [0, 1, 128, 255], 5)
