@@ -78,7 +78,8 @@ __device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i)
     return lo;
 }
 
-__device__ inline void load16(const uint32_t *w, int64_t i0, int64_t n, bool vec, uint32_t *r) {
+__device__ inline void load_items(const uint32_t *w, int64_t i0, int64_t n, bool vec,
+                                  uint32_t *r) {
     if (vec && i0 + ITEMS <= n) {
         const uint4 *p = reinterpret_cast<const uint4 *>(w + i0);
 #pragma unroll
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
     const int64_t base = t * TILE;
     const int64_t i0 = base + (int64_t)threadIdx.x * ITEMS;
     uint32_t r[ITEMS];
-    load16(a.w, i0, a.n_total, vec, r);
+    load_items(a.w, i0, a.n_total, vec, r);
     uint64_t sum = 0;
 #pragma unroll
     for (int e = 0; e < ITEMS; ++e) sum += r[e];
@@ -243,17 +244,20 @@ __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
 
 // ---------------------------------------------------------------------------
 // k_build_tile
+//
+// Phase 1 (thread t owns ITEMS consecutive leaves): prefix sums, keys and
+// cells into LDS, plus HALO leaves on either side of the tile.  Phase 2: the
+// levels of all boundaries held.  Phase 3 (node j = base + t + BT*k): the
+// node records and guide-table entries, so that each wave stores 64
+// consecutive 16-byte records (1 KiB) per instruction.
 // ---------------------------------------------------------------------------
-constexpr int LVL_N = TILE + 2 * HALO;  // boundaries base-HALO .. base+TILE+HALO-2
+constexpr int LEAF_N = TILE + 2 * HALO;  // leaves base-HALO .. base+TILE+HALO-1
+constexpr int LVL_N = LEAF_N - 1;        // boundaries base-HALO .. base+TILE+HALO-2
 
 struct TileSmem {
-    uint8_t lvl[LVL_N];
-    uint64_t first_key[BT];
-    int32_t first_cell[BT];
-    uint64_t last_key[BT];
-    int32_t last_cell[BT];
-    uint64_t hkey[2 * HALO];
-    int32_t hcell[2 * HALO];
+    uint64_t key[LEAF_N];
+    int32_t cell[LEAF_N];
+    uint8_t lvl[LVL_N + 1];
     uint64_t wave[BT / 64];
     int32_t ndefer;
     int64_t items[DEFER_CAP];
@@ -317,179 +321,126 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     const int tid = threadIdx.x;
     const int64_t t = blockIdx.x;
     const int64_t base = t * TILE;
-    const int64_t i0 = base + (int64_t)tid * ITEMS;
     const int64_t n = a.n_total;
-    const int64_t lb0 = base - HALO;             // lowest boundary held
+    const int64_t lb0 = base - HALO;             // lowest boundary (and leaf) held
     const int64_t lb1 = base + TILE + HALO - 2;  // highest boundary held
     if (tid == 0) sm.ndefer = 0;
 
-    // 1. weights and the global prefix of each element
-    uint32_t wv[ITEMS];
-    load16(a.w, i0, n, vec, wv);
-    uint64_t sum = 0;
-#pragma unroll
-    for (int e = 0; e < ITEMS; ++e) sum += wv[e];
-    uint64_t tile_total;
-    const uint64_t tp = a.tile_prefix[t];
-    uint64_t G = tp + block_excl_scan<BT / 64>(sum, sm.wave, tile_total);
-
-    // 2. keys and cells of the owned leaves
-    uint64_t key[ITEMS];
-    int32_t cell[ITEMS];
-    int32_t dcur = 0;
-    if (BATCHED) dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
-    Dist P = a.dists[dcur];
-    int64_t dend = P.eo + P.n;
-#pragma unroll
-    for (int e = 0; e < ITEMS; ++e) {
-        const int64_t i = i0 + e;
-        if (i < n) {
-            if (BATCHED) {
-                while (i >= dend) {
-                    ++dcur;
-                    P = a.dists[dcur];
-                    dend = P.eo + P.n;
-                }
-            }
-            Leaf L = make_leaf(G - P.G0, P);
-            key[e] = L.key;
-            cell[e] = L.cell;
-        } else {
-            key[e] = 0;
-            cell[e] = -2;
-        }
-        G += wv[e];
-    }
-    sm.first_key[tid] = key[0];
-    sm.first_cell[tid] = cell[0];
-    sm.last_key[tid] = key[ITEMS - 1];
-    sm.last_cell[tid] = cell[ITEMS - 1];
-
-    // 3. halo leaves: lanes 0..31 of wave 0 the HALO leaves left of the tile,
-    //    lanes 32..63 the HALO leaves right of it
-    if (tid < 64) {
-        const bool left = tid < HALO;
-        const int64_t i = left ? base - HALO + tid : base + TILE + (tid - HALO);
-        const bool exists = i >= 0 && i < n;
-        uint64_t wi = exists ? a.w[i] : 0u;
-        uint64_t suf = wave_incl_suffix(left ? wi : 0);
-        uint64_t pre = wave_incl_scan(left ? 0 : wi);
-        Leaf L;
-        L.key = 0;
-        L.cell = -2;
-        if (exists) {
-            uint64_t Gi = left ? tp - suf : tp + tile_total + pre - wi;
-            int32_t d = BATCHED ? find_segment(a.elem_off, a.D, i) : 0;
-            L = make_leaf(Gi - a.dists[d].G0, a.dists[d]);
-        }
-        sm.hkey[tid] = L.key;
-        sm.hcell[tid] = L.cell;
-    }
-    __syncthreads();
-
-    // 4. levels of all boundaries held in LDS
+    // ---- phase 1: keys and cells of the tile's leaves -----------------------
     {
-        Leaf nxt;
-        if (tid + 1 < BT) {
-            nxt.key = sm.first_key[tid + 1];
-            nxt.cell = sm.first_cell[tid + 1];
-        } else {
-            nxt.key = sm.hkey[HALO];
-            nxt.cell = sm.hcell[HALO];
-        }
+        const int64_t i0 = base + (int64_t)tid * ITEMS;
+        uint32_t wv[ITEMS];
+        load_items(a.w, i0, n, vec, wv);
+        uint64_t sum = 0;
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e) sum += wv[e];
+        uint64_t tile_total;
+        const uint64_t tp = a.tile_prefix[t];
+        uint64_t G = tp + block_excl_scan<BT / 64>(sum, sm.wave, tile_total);
+        int32_t dcur = 0;
+        if (BATCHED) dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
+        Dist P = a.dists[dcur];
+        int64_t dend = P.eo + P.n;
 #pragma unroll
         for (int e = 0; e < ITEMS; ++e) {
-            Leaf A{key[e], cell[e]};
-            Leaf B = (e + 1 < ITEMS) ? Leaf{key[e + 1], cell[e + 1]} : nxt;
-            sm.lvl[(i0 + e) - lb0] = (uint8_t)level_between(A, B);
+            const int64_t i = i0 + e;
+            Leaf L;
+            L.key = 0;
+            L.cell = -2;
+            if (i < n) {
+                if (BATCHED) {
+                    while (i >= dend) {
+                        ++dcur;
+                        P = a.dists[dcur];
+                        dend = P.eo + P.n;
+                    }
+                }
+                L = make_leaf(G - P.G0, P);
+            }
+            sm.key[i - lb0] = L.key;
+            sm.cell[i - lb0] = L.cell;
+            G += wv[e];
         }
-        if (tid < HALO) {  // boundaries base-HALO+tid, between halo leaves / tile leaf 0
-            Leaf A{sm.hkey[tid], sm.hcell[tid]};
-            Leaf B = (tid + 1 < HALO) ? Leaf{sm.hkey[tid + 1], sm.hcell[tid + 1]}
-                                      : Leaf{sm.first_key[0], sm.first_cell[0]};
-            sm.lvl[tid] = (uint8_t)level_between(A, B);
-        } else if (tid < 2 * HALO - 1) {  // boundaries base+TILE+(tid-HALO)
-            Leaf A{sm.hkey[tid], sm.hcell[tid]};
-            Leaf B{sm.hkey[tid + 1], sm.hcell[tid + 1]};
-            sm.lvl[TILE + tid] = (uint8_t)level_between(A, B);
+        // halo leaves: lanes 0..31 of wave 0 the HALO leaves left of the tile,
+        // lanes 32..63 the HALO leaves right of it
+        if (tid < 64) {
+            const bool left = tid < HALO;
+            const int64_t i = left ? base - HALO + tid : base + TILE + (tid - HALO);
+            const bool exists = i >= 0 && i < n;
+            uint64_t wi = exists ? a.w[i] : 0u;
+            uint64_t suf = wave_incl_suffix(left ? wi : 0);
+            uint64_t pre = wave_incl_scan(left ? 0 : wi);
+            Leaf L;
+            L.key = 0;
+            L.cell = -2;
+            if (exists) {
+                uint64_t Gi = left ? tp - suf : tp + tile_total + pre - wi;
+                int32_t d = BATCHED ? find_segment(a.elem_off, a.D, i) : 0;
+                L = make_leaf(Gi - a.dists[d].G0, a.dists[d]);
+            }
+            const int slot = left ? tid : TILE + tid;
+            sm.key[slot] = L.key;
+            sm.cell[slot] = L.cell;
         }
     }
     __syncthreads();
 
-    // 5. node records and guide-table entries of the owned nodes
-    Leaf prev;  // leaf i0 - 1
-    if (tid > 0) {
-        prev.key = sm.last_key[tid - 1];
-        prev.cell = sm.last_cell[tid - 1];
-    } else {
-        prev.key = sm.hkey[HALO - 1];
-        prev.cell = sm.hcell[HALO - 1];
+    // ---- phase 2: levels of all boundaries held ----------------------------
+    for (int b = tid; b < LVL_N; b += BT) {
+        Leaf A{sm.key[b], sm.cell[b]};
+        Leaf B{sm.key[b + 1], sm.cell[b + 1]};
+        sm.lvl[b] = (uint8_t)level_between(A, B);
     }
-    Leaf nxt;  // leaf i0 + ITEMS
-    if (tid + 1 < BT) {
-        nxt.key = sm.first_key[tid + 1];
-        nxt.cell = sm.first_cell[tid + 1];
-    } else {
-        nxt.key = sm.hkey[HALO];
-        nxt.cell = sm.hcell[HALO];
-    }
-    if (BATCHED) {
-        dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
-        P = a.dists[dcur];
-        dend = P.eo + P.n;
-    }
-#pragma unroll
-    for (int e = 0; e < ITEMS; ++e) {
-        const int64_t j = i0 + e;
+    __syncthreads();
+
+    // ---- phase 3: node records and guide-table entries ----------------------
+#pragma unroll 2
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t j = base + tid + (int64_t)BT * k;
         if (j >= n) break;
-        if (BATCHED) {
-            while (j >= dend) {
-                ++dcur;
-                P = a.dists[dcur];
-                dend = P.eo + P.n;
-            }
-        }
-        const int32_t pcell = (e > 0) ? cell[e - 1] : prev.cell;
-        const Leaf nx = (e + 1 < ITEMS) ? Leaf{key[e + 1], cell[e + 1]} : nxt;
-        const int l = sm.lvl[(j - 1) - lb0];
+        const int64_t lj = j - lb0;
+        const uint64_t kj = sm.key[lj];
+        const int32_t cj = sm.cell[lj];
         int32_t c0 = ~(int32_t)j, c1 = ~(int32_t)j;
         bool ok = true;
-        if (cell[e] >= 0) {
+        if (cj >= 0) {
+            const int l = sm.lvl[lj - 1];  // boundary j-1
             if (l == SENT) {
                 // first node of a cell: child 1 roots the cell's tree, child 0
                 // is the interval overlapping the cell from the left
-                c0 = (key[e] == 0) ? ~(int32_t)j : ~(int32_t)(j - 1);
+                c0 = (kj == 0) ? ~(int32_t)j : ~(int32_t)(j - 1);
                 ok = scan_right(sm.lvl, lb0, lb1, j, SENT, c1);
-                a.table[cell[e]] = (int32_t)j;
-                if (key[e] != 0 && cell[e] - pcell > 1) {
-                    if (cell[e] - pcell - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_HEAD);
-                    else fill_run(a.table, pcell + 1, cell[e], ~(int32_t)(j - 1));
+                a.table[cj] = (int32_t)j;
+                const int32_t pc = sm.cell[lj - 1];
+                if (kj != 0 && cj - pc > 1) {
+                    if (cj - pc - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_HEAD);
+                    else fill_run(a.table, pc + 1, cj, ~(int32_t)(j - 1));
                 }
             } else {
                 ok = scan_left(sm.lvl, lb0, j - 1, l, c0);
                 ok = ok && scan_right(sm.lvl, lb0, lb1, j, l, c1);
             }
             // the distribution's last leaf with mass covers the remaining cells
-            if (nx.cell < 0 || (nx.key == 0 && nx.cell != cell[e])) {
+            const int32_t nc = sm.cell[lj + 1];
+            const uint64_t nk = sm.key[lj + 1];
+            if (nc < 0 || (nk == 0 && nc != cj)) {
+                const Dist &P = a.dists[BATCHED ? find_segment(a.elem_off, a.D, j) : 0];
                 const int64_t cend = P.co + P.m;
-                if (cend - cell[e] > 1) {
-                    if (cend - cell[e] - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_TAIL);
-                    else fill_run(a.table, cell[e] + 1, cend, ~(int32_t)j);
+                if (cend - cj > 1) {
+                    if (cend - cj - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_TAIL);
+                    else fill_run(a.table, cj + 1, cend, ~(int32_t)j);
                 }
             }
         }
-        if (ok) {
-            store_node(a.nodes, j, key[e], c0, c1);
-        } else {
-            a.nodes[j].key = key[e];
-            push_item(sm, (j << 2) | ITEM_NODE);
-        }
+        if (!ok) push_item(sm, (j << 2) | ITEM_NODE);
+        // a deferred node's children are rewritten by the fix-up kernel
+        store_node(a.nodes, j, kj, c0, c1);
     }
     __syncthreads();
     const int32_t nd = sm.ndefer;
     if (tid == 0) a.defer_count[t] = nd;
     const int32_t nk = nd < DEFER_CAP ? nd : DEFER_CAP;
-    for (int32_t k = tid; k < nk; k += BT) a.defer_items[t * DEFER_CAP + k] = sm.items[k];
+    for (int32_t q = tid; q < nk; q += BT) a.defer_items[t * DEFER_CAP + q] = sm.items[q];
 }
 
 // ---------------------------------------------------------------------------

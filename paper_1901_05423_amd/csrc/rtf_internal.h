@@ -13,9 +13,9 @@ namespace rtf {
 // weights that carry mass (Alg. 1 sets the neighbour "to the maximum").
 constexpr int SENT = 65;
 
-// Build tile: 256 threads x 16 consecutive elements.
-constexpr int BT = 256;
-constexpr int ITEMS = 16;
+// Build tile: 512 threads x 8 consecutive elements.
+constexpr int BT = 512;
+constexpr int ITEMS = 8;
 constexpr int TILE = BT * ITEMS;
 // Leaves on either side of a tile whose keys are recomputed locally so that
 // subtree scans near the tile edges stay in LDS.

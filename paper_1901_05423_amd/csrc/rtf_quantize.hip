@@ -37,8 +37,10 @@ __global__ void k_qinit(double *scale, int32_t D) {
     if (d < D) scale[d] = 0.0;
 }
 
-// Blocks whose elements all lie in one distribution reduce in LDS and issue
-// one atomic; blocks that straddle distributions flush per lane and segment.
+// Element (t, k) of a block is b0 + t + QT*k, so every load and store of a
+// wave covers 64 consecutive elements.  Blocks whose elements all lie in one
+// distribution reduce in LDS and issue one atomic; blocks that straddle
+// distributions flush per lane and segment.
 __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
                                              const int64_t *__restrict__ off, int32_t D,
                                              int64_t n, double *scale, uint32_t *status) {
@@ -50,19 +52,21 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
     const bool one = !off || off[dfirst + 1] >= b1;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    const int64_t i0 = b0 + (int64_t)threadIdx.x * QI;
     int32_t d = dfirst;
-    if (!one && i0 < n) d = find_segment(off, D, i0);
     int64_t dend = off ? off[d + 1] : n;
     uint32_t mx = 0;
     bool bad = false;
-    for (int e = 0; e < QI && i0 + e < n; ++e) {
-        const int64_t i = i0 + e;
-        while (i >= dend) {
-            if (mx) atomicMax(max_word(scale, d), mx);
-            mx = 0;
-            ++d;
-            dend = off[d + 1];
+#pragma unroll 4
+    for (int k = 0; k < QI; ++k) {
+        const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
+        if (i >= b1) break;
+        if (!one) {
+            while (i >= dend) {
+                if (mx) atomicMax(max_word(scale, d), mx);
+                mx = 0;
+                ++d;
+                dend = off[d + 1];
+            }
         }
         const float x = v[i];
         if (!(x >= 0.0f) || isinf(x)) {
@@ -84,7 +88,13 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
         if (threadIdx.x == 0) {
             uint32_t m = 0;
             for (int w = 0; w < QT / 64; ++w) m = s_max[w] > m ? s_max[w] : m;
-            if (m) atomicMax(max_word(scale, dfirst), m);
+            // the maximum only grows, so a block whose value does not exceed
+            // what it reads skips the atomic (a stale read is low, which just
+            // means one more atomic); this keeps thousands of blocks of one
+            // large distribution from serialising on one address
+            const uint32_t seen = __hip_atomic_load(max_word(scale, dfirst), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+            if (m > seen) atomicMax(max_word(scale, dfirst), m);
             if (s_bad && status) atomicOr(status, status_bit(RTF_ERR_VALUE));
         }
     } else {
@@ -94,23 +104,30 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
     }
 }
 
+__device__ inline double scale_of(const double *scale, int32_t d) {
+    const float mx = __uint_as_float(*reinterpret_cast<const uint32_t *>(scale + d));
+    return mx > 0.0f ? 4294967295.0 / (double)mx : 0.0;
+}
+
 __global__ __launch_bounds__(QT) void k_qapply(const float *__restrict__ v,
                                                const int64_t *__restrict__ off, int32_t D,
                                                int64_t n, const double *scale,
                                                uint32_t *__restrict__ out) {
-    const int64_t i0 = ((int64_t)blockIdx.x * QT + threadIdx.x) * QI;
-    if (i0 >= n) return;
-    int32_t d = off ? find_segment(off, D, i0) : 0;
+    const int64_t b0 = (int64_t)blockIdx.x * QT * QI;
+    const int64_t b1 = b0 + (int64_t)QT * QI < n ? b0 + (int64_t)QT * QI : n;
+    int32_t d = off ? find_segment(off, D, b0) : 0;
     int64_t dend = off ? off[d + 1] : n;
-    float mx = __uint_as_float(*reinterpret_cast<const uint32_t *>(scale + d));
-    double s = mx > 0.0f ? 4294967295.0 / (double)mx : 0.0;
-    for (int e = 0; e < QI && i0 + e < n; ++e) {
-        const int64_t i = i0 + e;
-        while (i >= dend) {
-            ++d;
-            dend = off[d + 1];
-            mx = __uint_as_float(*reinterpret_cast<const uint32_t *>(scale + d));
-            s = mx > 0.0f ? 4294967295.0 / (double)mx : 0.0;
+    double s = scale_of(scale, d);
+#pragma unroll 4
+    for (int k = 0; k < QI; ++k) {
+        const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
+        if (i >= b1) break;
+        if (i >= dend) {
+            while (i >= dend) {
+                ++d;
+                dend = off[d + 1];
+            }
+            s = scale_of(scale, d);
         }
         const float x = v[i];
         uint32_t q = 0;
