@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = ("samples/s + build Melem/s at n=2^24 (% HBM peak) vs binary search, bit-exact")
 HBM_PEAK_GBS = 8000.0
-NODE_B, TABLE_B, U_B, IDX_B, X_B, W_B = 16, 4, 8, 4, 8, 4
+NODE_B, CELL_B, U_B, IDX_B, X_B, W_B = 16, 32, 8, 4, 8, 4
 
 
 def parse():
@@ -44,11 +44,19 @@ def parse():
     return p.parse_args()
 
 
-def mean_nodes_visited(key, child, table, m, u):
-    """Mean number of node records Alg. 2 reads per sample (host replay of the
-    descent on the exported forest for a subsample of the uniforms)."""
+def sample_bytes_model(key, child, table, m, u):
+    """Replay Alg. 2 on the host (exported forest, subsample of the uniforms)
+    and return the mean algorithmic bytes a sample reads beyond its streams:
+    the 32-byte cell record, plus 16 bytes per node record of the descent and
+    32 bytes for the two keys of the position when the cell record alone does
+    not resolve the sample; also the mean descent length and the fraction of
+    samples resolved by the cell record."""
     g = ((u.astype(object) * m) >> 64).astype(np.int64)
-    j = table[g].astype(np.int64)
+    ref = table[g].astype(np.int64)
+    deeper = (ref >= 0)
+    a = np.where(deeper, ref, 0)
+    deeper &= (u >= key[a]) & (child[a, 1] >= 0)
+    j = np.where(deeper, child[a, 1], -1).astype(np.int64)
     visits = np.zeros(u.size, np.int64)
     active = j >= 0
     while active.any():
@@ -57,7 +65,9 @@ def mean_nodes_visited(key, child, table, m, u):
         go_left = u[active] < key[ja]
         j[active] = np.where(go_left, child[ja, 0], child[ja, 1])
         active = j >= 0
-    return float(visits.mean())
+    extra = CELL_B + deeper * (NODE_B * visits + 2 * NODE_B)
+    return float(extra.mean()), float(visits[deeper].mean()) if deeper.any() else 0.0, \
+        float(1.0 - deeper.mean())
 
 
 def timed(fn, start, stop, reps):
@@ -149,10 +159,10 @@ def main():
     # position reads (one record pair)
     key, child, table, W = f.export()
     sub = u_h[:: max(1, S // (1 << 20))]
-    dbar = mean_nodes_visited(key, child, table, m, sub)
-    per_sample = U_B + IDX_B + X_B + TABLE_B + NODE_B * dbar + 2 * NODE_B
+    extra, dbar, resolved = sample_bytes_model(key, child, table, m, sub)
+    per_sample = U_B + IDX_B + X_B + extra
     sample_bytes = per_sample * S
-    build_bytes = (W_B + NODE_B) * n + TABLE_B * m
+    build_bytes = (W_B + NODE_B) * n + CELL_B * m
     achieved = sample_bytes / (t_sample * 1e-3) / 1e9
     result = {
         "metric": METRIC,
@@ -178,7 +188,8 @@ def main():
         "build_melem_s": n / (t_build * 1e-3) / 1e6,
         "build_hbm_frac": build_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "sample_only_samples_s": S / (t_sample * 1e-3),
-        "mean_nodes_per_sample": dbar,
+        "descent_nodes_when_needed": dbar,
+        "resolved_by_cell_record": resolved,
         "roofline": {
             "kernel": "k_sample (Alg. 2 descent + position)",
             "bound": "hbm",

@@ -60,13 +60,23 @@ typedef enum rtf_status {
 /*
  * Descriptor of a built forest.  Plain data: it holds pointers into the
  * caller's workspace and is valid while that workspace lives and is not used
- * for another build.  The node array holds n_total 16-byte records
- * { uint64 key U_j; int32 child[2]; } where node j splits between leaf j-1 and
- * leaf j and compares against U_j (Sec. 3.1).  A reference r >= 0 is a node, a
- * reference r < 0 is leaf ~r.  table[g] is a node (the first node of cell g,
- * whose child 1 roots the cell's tree and whose child 0 is the interval
+ * for another build.
+ *
+ * Node array: n_total 16-byte records { uint64 key U_j; int32 child[2]; }
+ * where node j splits between leaf j-1 and leaf j and compares against U_j
+ * (Sec. 3.1).  A reference r >= 0 is a node, a reference r < 0 is leaf ~r.
+ *
+ * Guide table: m_total 32-byte cell records
+ *   { uint64 k0, k1, k2; int32 ref; int32 c1; }.
+ * ref is the guide entry of Sec. 2.5 and 3.2: the first node a of cell g
+ * (whose child 1 roots the cell's tree and whose child 0 is the interval
  * overlapping the cell from the left) or, for a cell that no lower bound falls
- * in, the complement of the one leaf covering it (Sec. 3.2).
+ * in, the complement ~i of the one leaf covering it.  The other fields repeat
+ * keys and one child so that a sample whose cell holds at most one lower bound
+ * needs this record only: for ref = a, k0 = U_{a-1} (0 at a distribution
+ * start), k1 = U_a, k2 = U_{a+1}, c1 = child 1 of node a; for ref = ~i,
+ * k0 = U_i, k1 = U_{i+1}, k2 = 0, c1 = ref.  A key of all ones stands for the
+ * end of the distribution.
  */
 typedef struct rtf_forest {
     int32_t D;          /* number of distributions */
@@ -74,7 +84,7 @@ typedef struct rtf_forest {
     int64_t n_total;    /* leaves = nodes over all distributions */
     int64_t m_total;    /* guide cells over all distributions */
     void *nodes;        /* device: n_total node records */
-    int32_t *table;     /* device: m_total guide entries */
+    void *cells;        /* device: m_total guide cell records */
     void *dists;        /* device: D per-distribution parameter records */
     int64_t *elem_off;  /* device: D+1 element offsets (copied at build) */
     int64_t *cell_off;  /* device: D+1 cell offsets (copied at build) */
@@ -222,10 +232,10 @@ rtf_status rtf_backward(const rtf_forest *f, const int64_t *sample_off,
 rtf_status rtf_check(const rtf_forest *f, hipStream_t stream);
 
 /* Synchronise and copy the forest to host buffers (each may be NULL):
- * h_nodes receives the n_total 16-byte node records as stored (uint64 key,
- * int32 child 0, int32 child 1; 16 * n_total bytes), h_table int32[m_total],
- * h_W uint64[D] the distributions' total weights. */
-rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, int32_t *h_table,
+ * h_nodes receives the n_total 16-byte node records as stored, h_cells the
+ * m_total 32-byte guide cell records as stored, h_W uint64[D] the
+ * distributions' total weights. */
+rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, void *h_cells,
                              uint64_t *h_W, hipStream_t stream);
 
 /* Static string naming a status code. */

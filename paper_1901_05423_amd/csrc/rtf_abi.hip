@@ -15,7 +15,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace layout of a forest of D distributions, n_total leaves, m_total cells.
 struct Layout {
-    size_t status, nodes, table, dists, eoff, coff, tsum, tpre, dloc, dcnt, ditems, total;
+    size_t status, nodes, cells, dists, eoff, coff, tsum, tpre, dloc, dcnt, ditems, total;
     int64_t ntiles;
 };
 
@@ -27,8 +27,8 @@ Layout make_layout(int32_t D, int64_t n, int64_t m) {
     o = align256(o + 256);
     L.nodes = o;
     o = align256(o + sizeof(Node) * (size_t)n);
-    L.table = o;
-    o = align256(o + sizeof(int32_t) * (size_t)m);
+    L.cells = o;
+    o = align256(o + sizeof(Cell) * (size_t)m);
     L.dists = o;
     o = align256(o + sizeof(Dist) * (size_t)D);
     L.eoff = o;
@@ -78,7 +78,7 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     f.n_total = n;
     f.m_total = m;
     f.nodes = b + L.nodes;
-    f.table = reinterpret_cast<int32_t *>(b + L.table);
+    f.cells = b + L.cells;
     f.dists = b + L.dists;
     f.elem_off = reinterpret_cast<int64_t *>(b + L.eoff);
     f.cell_off = reinterpret_cast<int64_t *>(b + L.coff);
@@ -98,7 +98,7 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     a.m_total = m;
     a.ntiles = L.ntiles;
     a.nodes = static_cast<Node *>(f.nodes);
-    a.table = f.table;
+    a.cells = static_cast<Cell *>(f.cells);
     a.dists = static_cast<Dist *>(f.dists);
     a.status = f.status;
     a.tile_sum = reinterpret_cast<uint64_t *>(b + L.tsum);
@@ -113,7 +113,7 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
 }
 
 bool forest_ok(const rtf_forest *f) {
-    return f && f->nodes && f->table && f->dists && f->status && f->D >= 1 &&
+    return f && f->nodes && f->cells && f->dists && f->status && f->D >= 1 &&
            sizes_ok(f->D, f->n_total, f->m_total);
 }
 
@@ -157,7 +157,8 @@ rtf_status rtf_sample(const rtf_forest *f, const uint64_t *u, int64_t S, int32_t
                       double *out_x, hipStream_t stream) {
     if (!forest_ok(f) || !sample_args_ok(u, S, out_idx, out_x)) return RTF_ERR_INVALID_ARG;
     if (S == 0) return RTF_OK;
-    return from_hip(launch_sample(static_cast<const Node *>(f->nodes), f->table,
+    return from_hip(launch_sample(static_cast<const Node *>(f->nodes),
+                                  static_cast<const Cell *>(f->cells),
                                   static_cast<const Dist *>(f->dists), nullptr, 1, f->n_total, u, S,
                                   out_idx, out_x, stream));
 }
@@ -167,7 +168,8 @@ rtf_status rtf_sample_batched(const rtf_forest *f, const int64_t *sample_off, co
     if (!forest_ok(f) || !sample_args_ok(u, S, out_idx, out_x)) return RTF_ERR_INVALID_ARG;
     if (!sample_off || !aligned(sample_off, 8)) return RTF_ERR_INVALID_ARG;
     if (S == 0) return RTF_OK;
-    return from_hip(launch_sample(static_cast<const Node *>(f->nodes), f->table,
+    return from_hip(launch_sample(static_cast<const Node *>(f->nodes),
+                                  static_cast<const Cell *>(f->cells),
                                   static_cast<const Dist *>(f->dists), sample_off, f->D, f->n_total,
                                   u, S, out_idx, out_x, stream));
 }
@@ -177,7 +179,8 @@ rtf_status rtf_sample_2d(const rtf_forest *f, const uint64_t *u2, int64_t S, int
     if (!forest_ok(f) || f->D < 2 || !sample_args_ok(u2, S, out_rc, out_xy))
         return RTF_ERR_INVALID_ARG;
     if (S == 0) return RTF_OK;
-    return from_hip(launch_sample_2d(static_cast<const Node *>(f->nodes), f->table,
+    return from_hip(launch_sample_2d(static_cast<const Node *>(f->nodes),
+                                  static_cast<const Cell *>(f->cells),
                                      static_cast<const Dist *>(f->dists), f->D, f->n_total, u2, S,
                                      out_rc, out_xy, stream));
 }
@@ -186,7 +189,8 @@ rtf_status rtf_sample_bsearch(const rtf_forest *f, const uint64_t *u, int64_t S,
                               int32_t *out_idx, double *out_x, hipStream_t stream) {
     if (!forest_ok(f) || !sample_args_ok(u, S, out_idx, out_x)) return RTF_ERR_INVALID_ARG;
     if (S == 0) return RTF_OK;
-    return from_hip(launch_sample_bsearch(static_cast<const Node *>(f->nodes), f->table,
+    return from_hip(launch_sample_bsearch(static_cast<const Node *>(f->nodes),
+                                  static_cast<const Cell *>(f->cells),
                                           static_cast<const Dist *>(f->dists), false, u, S,
                                           out_idx, out_x, stream));
 }
@@ -195,7 +199,8 @@ rtf_status rtf_sample_cutpoint_bsearch(const rtf_forest *f, const uint64_t *u, i
                                        int32_t *out_idx, double *out_x, hipStream_t stream) {
     if (!forest_ok(f) || !sample_args_ok(u, S, out_idx, out_x)) return RTF_ERR_INVALID_ARG;
     if (S == 0) return RTF_OK;
-    return from_hip(launch_sample_bsearch(static_cast<const Node *>(f->nodes), f->table,
+    return from_hip(launch_sample_bsearch(static_cast<const Node *>(f->nodes),
+                                  static_cast<const Cell *>(f->cells),
                                           static_cast<const Dist *>(f->dists), true, u, S,
                                           out_idx, out_x, stream));
 }
@@ -248,14 +253,14 @@ rtf_status rtf_check(const rtf_forest *f, hipStream_t stream) {
     return RTF_OK;
 }
 
-rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, int32_t *h_table,
-                             uint64_t *h_W, hipStream_t stream) {
+rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, void *h_cells, uint64_t *h_W,
+                             hipStream_t stream) {
     if (!forest_ok(f)) return RTF_ERR_INVALID_ARG;
     if (hipStreamSynchronize(stream) != hipSuccess) return RTF_ERR_HIP;
     if (h_nodes && hipMemcpy(h_nodes, f->nodes, sizeof(Node) * (size_t)f->n_total,
                              hipMemcpyDeviceToHost) != hipSuccess)
         return RTF_ERR_HIP;
-    if (h_table && hipMemcpy(h_table, f->table, sizeof(int32_t) * (size_t)f->m_total,
+    if (h_cells && hipMemcpy(h_cells, f->cells, sizeof(Cell) * (size_t)f->m_total,
                              hipMemcpyDeviceToHost) != hipSuccess)
         return RTF_ERR_HIP;
     if (h_W) {

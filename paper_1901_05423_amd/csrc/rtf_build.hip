@@ -120,6 +120,28 @@ __device__ inline Leaf make_leaf(uint64_t C, const Dist &P) {
     return L;
 }
 
+__device__ inline void store_cell(Cell *cells, int64_t g, uint64_t k0, uint64_t k1, uint64_t k2,
+                                  int32_t ref, int32_t c1) {
+    uint4 a, b;
+    a.x = (uint32_t)k0;
+    a.y = (uint32_t)(k0 >> 32);
+    a.z = (uint32_t)k1;
+    a.w = (uint32_t)(k1 >> 32);
+    b.x = (uint32_t)k2;
+    b.y = (uint32_t)(k2 >> 32);
+    b.z = (uint32_t)ref;
+    b.w = (uint32_t)c1;
+    uint4 *p = reinterpret_cast<uint4 *>(cells + g);
+    p[0] = a;
+    p[1] = b;
+}
+
+// cells [c_lo, c_hi) covered by interval i alone, whose keys are lo and hi
+__device__ inline void fill_run(Cell *cells, int64_t c_lo, int64_t c_hi, int32_t i, uint64_t lo,
+                                uint64_t hi) {
+    for (int64_t c = c_lo; c < c_hi; ++c) store_cell(cells, c, lo, hi, 0, ~i, ~i);
+}
+
 __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t c0, int32_t c1) {
     uint4 v;
     v.x = (uint32_t)key;
@@ -311,10 +333,6 @@ __device__ inline bool scan_right(const uint8_t *lvl, int64_t lb0, int64_t lb1, 
     return true;
 }
 
-__device__ inline void fill_run(int32_t *table, int64_t c_lo, int64_t c_hi, int32_t val) {
-    for (int64_t c = c_lo; c < c_hi; ++c) table[c] = val;
-}
-
 template <bool BATCHED>
 __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     __shared__ TileSmem sm;
@@ -405,30 +423,34 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
         bool ok = true;
         if (cj >= 0) {
             const int l = sm.lvl[lj - 1];  // boundary j-1
+            // leaf j+1 carries mass and belongs to j's distribution
+            const int32_t nc = sm.cell[lj + 1];
+            const uint64_t nk = sm.key[lj + 1];
+            const bool next_same = nc >= 0 && !(nk == 0 && nc != cj);
             if (l == SENT) {
                 // first node of a cell: child 1 roots the cell's tree, child 0
                 // is the interval overlapping the cell from the left
+                const uint64_t kp = sm.key[lj - 1];
                 c0 = (kj == 0) ? ~(int32_t)j : ~(int32_t)(j - 1);
                 ok = scan_right(sm.lvl, lb0, lb1, j, SENT, c1);
-                a.table[cj] = (int32_t)j;
+                store_cell(a.cells, cj, kj == 0 ? 0 : kp, kj, next_same ? nk : KEY_END,
+                           (int32_t)j, c1);
                 const int32_t pc = sm.cell[lj - 1];
                 if (kj != 0 && cj - pc > 1) {
                     if (cj - pc - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_HEAD);
-                    else fill_run(a.table, pc + 1, cj, ~(int32_t)(j - 1));
+                    else fill_run(a.cells, pc + 1, cj, (int32_t)(j - 1), kp, kj);
                 }
             } else {
                 ok = scan_left(sm.lvl, lb0, j - 1, l, c0);
                 ok = ok && scan_right(sm.lvl, lb0, lb1, j, l, c1);
             }
             // the distribution's last leaf with mass covers the remaining cells
-            const int32_t nc = sm.cell[lj + 1];
-            const uint64_t nk = sm.key[lj + 1];
-            if (nc < 0 || (nk == 0 && nc != cj)) {
+            if (!next_same) {
                 const Dist &P = a.dists[BATCHED ? find_segment(a.elem_off, a.D, j) : 0];
                 const int64_t cend = P.co + P.m;
                 if (cend - cj > 1) {
                     if (cend - cj - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_TAIL);
-                    else fill_run(a.table, cj + 1, cend, ~(int32_t)j);
+                    else fill_run(a.cells, cj + 1, cend, (int32_t)j, kj, KEY_END);
                 }
             }
         }
@@ -528,43 +550,61 @@ struct GlobalView {
         }
         return (int32_t)(g + 1);
     }
-    // the record of node j
-    __device__ void node(int64_t j, uint64_t &kj, int32_t &c0, int32_t &c1) const {
+    // leaf j+1 carries mass and belongs to the distribution of leaf j
+    __device__ bool next_same(const Leaf &Lj, const Leaf &Ln) const {
+        return Ln.cell >= 0 && !(Ln.key == 0 && Ln.cell != Lj.cell);
+    }
+    // the record of node j, and whether j is the first node of its cell
+    __device__ bool node(int64_t j, uint64_t &kj, int32_t &c0, int32_t &c1) const {
         Leaf Lj = leaf(j);
         kj = Lj.key;
         c0 = c1 = ~(int32_t)j;
-        if (Lj.cell < 0) return;
+        if (Lj.cell < 0) return false;
         Leaf Lp = leaf(j - 1);
         int l = level_between(Lp, Lj);
         if (l == SENT) {
             c0 = (Lj.key == 0) ? ~(int32_t)j : ~(int32_t)(j - 1);
             int64_t b = extend_right(j, Lj.key, Lj.cell, 64);
             c1 = root(j, b);
-        } else {
-            const int64_t k = j - 1;
-            int64_t lo = extend_left(k, Lp.key, Lp.cell, l);
-            int64_t hi = (l == 0) ? j : extend_right(j, Lp.key, Lp.cell, l);
-            c0 = root(lo, k);
-            c1 = root(j, hi);
+            return true;
         }
+        const int64_t k = j - 1;
+        int64_t lo = extend_left(k, Lp.key, Lp.cell, l);
+        int64_t hi = (l == 0) ? j : extend_right(j, Lp.key, Lp.cell, l);
+        c0 = root(lo, k);
+        c1 = root(j, hi);
+        return false;
     }
-    // guide-table runs owned by node / leaf j: [lo, hi) filled with val
-    __device__ bool head_run(int64_t j, int64_t &lo, int64_t &hi, int32_t &val) const {
+    // the guide cell record of the cell whose first node is j
+    __device__ void root_cell(int64_t j, int32_t c1) const {
+        Leaf Lj = leaf(j), Ln = leaf(j + 1);
+        const uint64_t k0 = (Lj.key == 0) ? 0 : a.nodes[j - 1].key;
+        store_cell(a.cells, Lj.cell, k0, Lj.key, next_same(Lj, Ln) ? Ln.key : KEY_END,
+                   (int32_t)j, c1);
+    }
+    // guide-table runs owned by node / leaf j: cells [lo, hi) covered by
+    // interval i with keys k0, k1
+    __device__ bool head_run(int64_t j, int64_t &lo, int64_t &hi, int32_t &i, uint64_t &k0,
+                             uint64_t &k1) const {
         Leaf Lj = leaf(j), Lp = leaf(j - 1);
         if (Lj.cell < 0 || Lj.key == 0 || level_between(Lp, Lj) != SENT) return false;
         lo = (int64_t)Lp.cell + 1;
         hi = Lj.cell;
-        val = ~(int32_t)(j - 1);
+        i = (int32_t)(j - 1);
+        k0 = Lp.key;
+        k1 = Lj.key;
         return hi > lo;
     }
-    __device__ bool tail_run(int64_t j, int64_t &lo, int64_t &hi, int32_t &val) const {
+    __device__ bool tail_run(int64_t j, int64_t &lo, int64_t &hi, int32_t &i, uint64_t &k0,
+                             uint64_t &k1) const {
         Leaf Lj = leaf(j), Ln = leaf(j + 1);
-        if (Lj.cell < 0) return false;
-        if (!(Ln.cell < 0 || (Ln.key == 0 && Ln.cell != Lj.cell))) return false;
+        if (Lj.cell < 0 || next_same(Lj, Ln)) return false;
         const Dist &P = a.dists[dist_of(j)];
         lo = (int64_t)Lj.cell + 1;
         hi = P.co + P.m;
-        val = ~(int32_t)j;
+        i = (int32_t)j;
+        k0 = Lj.key;
+        k1 = KEY_END;
         return hi > lo;
     }
 };
@@ -573,7 +613,7 @@ template <bool BATCHED>
 __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
     __shared__ int64_t s_item[DEFER_CAP];
     __shared__ int32_t s_nrun;
-    __shared__ int64_t s_run[3];
+    __shared__ uint64_t s_run[5];
     const int64_t t = blockIdx.x;
     const int32_t cnt = a.defer_count[t];
     if (cnt == 0) return;
@@ -584,12 +624,13 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
         for (int64_t j = base + threadIdx.x; j < base + TILE && j < a.n_total; j += BT) {
             uint64_t kj;
             int32_t c0, c1;
-            gv.node(j, kj, c0, c1);
+            if (gv.node(j, kj, c0, c1)) gv.root_cell(j, c1);
             store_node(a.nodes, j, kj, c0, c1);
             int64_t lo, hi;
-            int32_t val;
-            if (gv.head_run(j, lo, hi, val)) fill_run(a.table, lo, hi, val);
-            if (gv.tail_run(j, lo, hi, val)) fill_run(a.table, lo, hi, val);
+            int32_t i;
+            uint64_t k0, k1;
+            if (gv.head_run(j, lo, hi, i, k0, k1)) fill_run(a.cells, lo, hi, i, k0, k1);
+            if (gv.tail_run(j, lo, hi, i, k0, k1)) fill_run(a.cells, lo, hi, i, k0, k1);
         }
         return;
     }
@@ -601,7 +642,7 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
         if ((it & 3) == ITEM_NODE) {
             uint64_t kj;
             int32_t c0, c1;
-            gv.node(j, kj, c0, c1);
+            if (gv.node(j, kj, c0, c1)) gv.root_cell(j, c1);
             store_node(a.nodes, j, kj, c0, c1);
         } else {
             s_item[atomicAdd(&s_nrun, 1)] = it;
@@ -612,17 +653,21 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
     for (int32_t r = 0; r < nr; ++r) {
         if (threadIdx.x == 0) {
             int64_t it = s_item[r], lo = 0, hi = 0;
-            int32_t val = 0;
-            bool has = ((it & 3) == ITEM_HEAD) ? gv.head_run(it >> 2, lo, hi, val)
-                                               : gv.tail_run(it >> 2, lo, hi, val);
-            s_run[0] = has ? lo : 0;
-            s_run[1] = has ? hi : 0;
-            s_run[2] = val;
+            int32_t i = 0;
+            uint64_t k0 = 0, k1 = 0;
+            bool has = ((it & 3) == ITEM_HEAD) ? gv.head_run(it >> 2, lo, hi, i, k0, k1)
+                                               : gv.tail_run(it >> 2, lo, hi, i, k0, k1);
+            s_run[0] = has ? (uint64_t)lo : 0;
+            s_run[1] = has ? (uint64_t)hi : 0;
+            s_run[2] = (uint64_t)(uint32_t)i;
+            s_run[3] = k0;
+            s_run[4] = k1;
         }
         __syncthreads();
-        const int64_t lo = s_run[0], hi = s_run[1];
-        const int32_t val = (int32_t)s_run[2];
-        for (int64_t c = lo + threadIdx.x; c < hi; c += BT) a.table[c] = val;
+        const int64_t lo = (int64_t)s_run[0], hi = (int64_t)s_run[1];
+        const int32_t i = (int32_t)(uint32_t)s_run[2];
+        const uint64_t k0 = s_run[3], k1 = s_run[4];
+        for (int64_t c = lo + threadIdx.x; c < hi; c += BT) store_cell(a.cells, c, k0, k1, 0, ~i, ~i);
         __syncthreads();
     }
 }

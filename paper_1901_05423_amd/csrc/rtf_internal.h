@@ -37,6 +37,20 @@ struct alignas(16) Node {
     int32_t c0, c1;
 };
 
+// Guide-table cell record.  `ref` is the paper's guide entry (Sec. 2.5, 3.2):
+// the cell's first node a, or ~i when one interval i covers the whole cell.
+// The keys needed to finish the common cases are stored beside it, so that a
+// sample whose cell holds at most one lower bound reads one 32-byte record:
+//   ref = a >= 0:  k0 = U_{a-1} (0 at a distribution start), k1 = U_a,
+//                  k2 = U_{a+1} or KEY_END, c1 = child 1 of node a;
+//   ref = ~i < 0:  k0 = U_i, k1 = U_{i+1} or KEY_END, k2 = 0, c1 = ref.
+// KEY_END stands for the upper end of the distribution (partial sum W).
+struct alignas(32) Cell {
+    uint64_t k0, k1, k2;
+    int32_t ref, c1;
+};
+constexpr uint64_t KEY_END = ~0ull;
+
 // Per-distribution parameters, written by the build's scan kernel.
 struct alignas(64) Dist {
     uint64_t W;   // total weight
@@ -63,7 +77,7 @@ struct BuildArgs {
     int64_t m_total;
     int64_t ntiles;
     Node *nodes;
-    int32_t *table;
+    Cell *cells;
     Dist *dists;
     uint32_t *status;
     uint64_t *tile_sum;     // [ntiles]
@@ -126,14 +140,14 @@ __host__ __device__ inline int level_of(uint64_t a, uint64_t b) { return 64 - cl
 // ---- launchers (defined in the .hip files) ----------------------------------
 
 hipError_t launch_build(const BuildArgs &a, hipStream_t st);
-hipError_t launch_sample(const Node *nodes, const int32_t *table, const Dist *dists,
+hipError_t launch_sample(const Node *nodes, const Cell *cells, const Dist *dists,
                          const int64_t *sample_off, int32_t D, int64_t n_total,
                          const uint64_t *u, int64_t S, int32_t *idx, double *x,
                          hipStream_t st);
-hipError_t launch_sample_2d(const Node *nodes, const int32_t *table, const Dist *dists,
+hipError_t launch_sample_2d(const Node *nodes, const Cell *cells, const Dist *dists,
                             int32_t D, int64_t n_total, const uint64_t *u2, int64_t S,
                             int32_t *rc, double *xy, hipStream_t st);
-hipError_t launch_sample_bsearch(const Node *nodes, const int32_t *table,
+hipError_t launch_sample_bsearch(const Node *nodes, const Cell *cells,
                                  const Dist *dists, bool cutpoint, const uint64_t *u,
                                  int64_t S, int32_t *idx, double *x, hipStream_t st);
 hipError_t launch_copy_offsets(const int64_t *src_e, const int64_t *src_c, int64_t *dst_e,

@@ -27,40 +27,92 @@ __device__ inline Node load_node(const Node *nodes, int64_t j) {
     return r;
 }
 
+__device__ inline Cell load_cell(const Cell *cells, int64_t g) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(cells + g);
+    const uint4 a = p[0], b = p[1];
+    Cell c;
+    c.k0 = ((uint64_t)a.y << 32) | a.x;
+    c.k1 = ((uint64_t)a.w << 32) | a.z;
+    c.k2 = ((uint64_t)b.y << 32) | b.x;
+    c.ref = (int32_t)b.z;
+    c.c1 = (int32_t)b.w;
+    return c;
+}
+
+// A sampled leaf with the keys of its interval's two ends (KEY_END for the
+// distribution's end); leaf -1 flags a damaged workspace.
+struct Hit {
+    int64_t i;
+    uint64_t lo, hi;
+};
+
 // Alg. 2: g = floor(xi * m); follow the reference until it names a leaf.
-// A reference outside the forest, or a path longer than the forest has
-// nodes, can only come from a damaged workspace; it yields -1.
-__device__ inline int64_t descend(const Node *nodes, const int32_t *table, const Dist &P,
-                                  uint64_t u, int64_t n_total) {
-    int32_t j = table[P.co + (int64_t)mulhi64(u, (uint64_t)P.m)];
-    for (int64_t steps = 0; j >= 0; ++steps) {
-        if (j >= n_total || steps > n_total) return -1;
-        Node nd = load_node(nodes, j);
-        j = (u < nd.key) ? nd.c0 : nd.c1;
+// The cell record resolves the guide step and, for a cell that holds at most
+// one lower bound, the whole sample; otherwise the descent continues from the
+// cell's tree root.  A reference outside the forest, or a path longer than
+// the forest has nodes, can only come from a damaged workspace.
+__device__ inline Hit descend(const Node *nodes, const Cell *cells, const Dist &P, uint64_t u,
+                              int64_t n_total) {
+    const Cell c = load_cell(cells, P.co + (int64_t)mulhi64(u, (uint64_t)P.m));
+    Hit h;
+    if (c.ref < 0) {  // one interval covers the cell
+        h.i = ~(int64_t)c.ref;
+        h.lo = c.k0;
+        h.hi = c.k1;
+    } else if (u < c.k1) {  // child 0 of the cell's first node: its left neighbour
+        h.i = (int64_t)c.ref - 1;
+        h.lo = c.k0;
+        h.hi = c.k1;
+    } else if (c.c1 < 0) {  // the cell's tree is a single leaf
+        h.i = ~(int64_t)c.c1;
+        h.lo = c.k1;
+        h.hi = c.k2;
+    } else {
+        int32_t j = c.c1;
+        for (int64_t steps = 0; j >= 0; ++steps) {
+            if (j >= n_total || steps > n_total) {
+                h.i = -1;
+                return h;
+            }
+            const Node nd = load_node(nodes, j);
+            j = (u < nd.key) ? nd.c0 : nd.c1;
+        }
+        h.i = ~(int64_t)j;
+        if (h.i < P.eo || h.i >= P.eo + P.n) {
+            h.i = -1;
+            return h;
+        }
+        h.lo = nodes[h.i].key;
+        h.hi = (h.i + 1 < P.eo + P.n) ? nodes[h.i + 1].key : KEY_END;
     }
-    const int64_t i = (int64_t)(~j);
-    return (i >= P.eo && i < P.eo + P.n) ? i : -1;
+    if (h.i < P.eo || h.i >= P.eo + P.n) h.i = -1;
+    return h;
 }
 
 // x = (i + ((t - C_i) + lo * 2^-64) / w_i) / n with t:lo = u * W, where
-// C_i = floor(U_i * W / 2^64) recovers the exact partial sum from the key.
-__device__ inline double position(const Node *nodes, const Dist &P, int64_t i, uint64_t u) {
+// C_i = floor(U_i * W / 2^64) recovers the exact partial sum from a key.
+__device__ inline double position(const Dist &P, const Hit &h, uint64_t u) {
     const uint64_t W = P.W;
-    const uint64_t Ci = mulhi64(nodes[i].key, W);
-    uint64_t Cn = W;
-    if (i + 1 < P.eo + P.n) {
-        uint64_t k1 = nodes[i + 1].key;
-        if (k1 != ~0ull) Cn = mulhi64(k1, W);
-    }
+    const uint64_t Ci = mulhi64(h.lo, W);
+    const uint64_t Cn = (h.hi == KEY_END) ? W : mulhi64(h.hi, W);
     const uint64_t t = mulhi64(u, W);
     const uint64_t lo = u * W;
     const double frac = ((double)(t - Ci) + ldexp((double)lo, -64)) / (double)(Cn - Ci);
-    return ((double)(i - P.eo) + frac) / (double)P.n;
+    return ((double)(h.i - P.eo) + frac) / (double)P.n;
+}
+
+// The same, for a leaf found without its keys (the baselines).
+__device__ inline double position_of(const Node *nodes, const Dist &P, int64_t i, uint64_t u) {
+    Hit h;
+    h.i = i;
+    h.lo = nodes[i].key;
+    h.hi = (i + 1 < P.eo + P.n) ? nodes[i + 1].key : KEY_END;
+    return position(P, h, u);
 }
 
 template <bool BATCHED, bool WANT_X>
 __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
-                                                const int32_t *__restrict__ table,
+                                                const Cell *__restrict__ cells,
                                                 const Dist *__restrict__ dists,
                                                 const int64_t *__restrict__ sample_off,
                                                 int32_t D, int64_t n_total,
@@ -72,20 +124,22 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
         const int32_t d = BATCHED ? find_segment(sample_off, D, s) : 0;
         const Dist &P = dists[d];
         const uint64_t us = __builtin_nontemporal_load(u + s);
-        const int64_t i = (P.flags & DIST_ZERO) ? -1 : descend(nodes, table, P, us, n_total);
-        if (i < 0) {
+        Hit h;
+        h.i = -1;
+        if (!(P.flags & DIST_ZERO)) h = descend(nodes, cells, P, us, n_total);
+        if (h.i < 0) {
             idx[s] = -1;
             if (WANT_X) x[s] = __builtin_nan("");
             continue;
         }
-        __builtin_nontemporal_store((int32_t)(i - P.eo), idx + s);
-        if (WANT_X) __builtin_nontemporal_store(position(nodes, P, i, us), x + s);
+        __builtin_nontemporal_store((int32_t)(h.i - P.eo), idx + s);
+        if (WANT_X) __builtin_nontemporal_store(position(P, h, us), x + s);
     }
 }
 
 template <bool WANT_X>
 __global__ __launch_bounds__(256) void k_sample_2d(const Node *__restrict__ nodes,
-                                                   const int32_t *__restrict__ table,
+                                                   const Cell *__restrict__ cells,
                                                    const Dist *__restrict__ dists, int32_t D,
                                                    int64_t n_total,
                                                    const uint64_t *__restrict__ u2, int64_t S,
@@ -95,25 +149,29 @@ __global__ __launch_bounds__(256) void k_sample_2d(const Node *__restrict__ node
     const Dist &M = dists[0];
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
         const uint64_t ur = u2[2 * s], uc = u2[2 * s + 1];
-        const int64_t ig = (M.flags & DIST_ZERO) ? -1 : descend(nodes, table, M, ur, n_total);
-        const int64_t r = ig - M.eo;
+        Hit hr;
+        hr.i = -1;
+        if (!(M.flags & DIST_ZERO)) hr = descend(nodes, cells, M, ur, n_total);
+        const int64_t r = hr.i - M.eo;
         // the marginal must have one weight per row distribution 1..D-1
-        if (ig < 0 || 1 + r >= D) {
+        if (hr.i < 0 || 1 + r >= D) {
             rc[2 * s] = rc[2 * s + 1] = -1;
             if (WANT_X) xy[2 * s] = xy[2 * s + 1] = __builtin_nan("");
             continue;
         }
         rc[2 * s] = (int32_t)r;
-        if (WANT_X) xy[2 * s] = position(nodes, M, ig, ur);
+        if (WANT_X) xy[2 * s] = position(M, hr, ur);
         const Dist &R = dists[1 + r];
-        const int64_t jg = (R.flags & DIST_ZERO) ? -1 : descend(nodes, table, R, uc, n_total);
-        if (jg < 0) {
+        Hit hc;
+        hc.i = -1;
+        if (!(R.flags & DIST_ZERO)) hc = descend(nodes, cells, R, uc, n_total);
+        if (hc.i < 0) {
             rc[2 * s + 1] = -1;
             if (WANT_X) xy[2 * s + 1] = __builtin_nan("");
             continue;
         }
-        rc[2 * s + 1] = (int32_t)(jg - R.eo);
-        if (WANT_X) xy[2 * s + 1] = position(nodes, R, jg, uc);
+        rc[2 * s + 1] = (int32_t)(hc.i - R.eo);
+        if (WANT_X) xy[2 * s + 1] = position(R, hc, uc);
     }
 }
 
@@ -133,7 +191,7 @@ __device__ inline int64_t bisect(const Node *nodes, int64_t lo, int64_t hi, uint
 
 template <bool CUTPOINT, bool WANT_X>
 __global__ __launch_bounds__(256) void k_sample_bsearch(const Node *__restrict__ nodes,
-                                                        const int32_t *__restrict__ table,
+                                                        const Cell *__restrict__ cells,
                                                         const Dist *__restrict__ dists,
                                                         const uint64_t *__restrict__ u,
                                                         int64_t S, int32_t *__restrict__ idx,
@@ -153,13 +211,13 @@ __global__ __launch_bounds__(256) void k_sample_bsearch(const Node *__restrict__
             // the cell's first overlapping interval bounds the search from
             // below, the next cell's first overlapping interval from above
             const int64_t g = (int64_t)mulhi64(us, (uint64_t)P.m);
-            const int32_t r0 = table[P.co + g];
+            const int32_t r0 = cells[P.co + g].ref;
             if (r0 < 0) {
                 lo = hi = ~r0;
             } else {
                 lo = (r0 > P.eo) ? r0 - 1 : r0;
                 if (g + 1 < P.m) {
-                    const int32_t r1 = table[P.co + g + 1];
+                    const int32_t r1 = cells[P.co + g + 1].ref;
                     hi = (r1 < 0) ? ~r1 : r1;
                 }
             }
@@ -168,7 +226,7 @@ __global__ __launch_bounds__(256) void k_sample_bsearch(const Node *__restrict__
         hi = hi < lo ? lo : (hi > last ? last : hi);
         const int64_t i = (lo == hi) ? lo : bisect(nodes, lo, hi, us);
         idx[s] = (int32_t)(i - P.eo);
-        if (WANT_X) x[s] = position(nodes, P, i, us);
+        if (WANT_X) x[s] = position_of(nodes, P, i, us);
     }
 }
 
@@ -180,55 +238,55 @@ inline int grid_for(int64_t S) {
 
 }  // namespace
 
-hipError_t launch_sample(const Node *nodes, const int32_t *table, const Dist *dists,
+hipError_t launch_sample(const Node *nodes, const Cell *cells, const Dist *dists,
                          const int64_t *sample_off, int32_t D, int64_t n_total,
                          const uint64_t *u, int64_t S, int32_t *idx, double *x,
                          hipStream_t st) {
     const dim3 g(grid_for(S)), b(256);
     const bool batched = sample_off != nullptr;
     if (batched && x)
-        hipLaunchKernelGGL((k_sample<true, true>), g, b, 0, st, nodes, table, dists, sample_off,
+        hipLaunchKernelGGL((k_sample<true, true>), g, b, 0, st, nodes, cells, dists, sample_off,
                            D, n_total, u, S, idx, x);
     else if (batched)
-        hipLaunchKernelGGL((k_sample<true, false>), g, b, 0, st, nodes, table, dists,
+        hipLaunchKernelGGL((k_sample<true, false>), g, b, 0, st, nodes, cells, dists,
                            sample_off, D, n_total, u, S, idx, x);
     else if (x)
-        hipLaunchKernelGGL((k_sample<false, true>), g, b, 0, st, nodes, table, dists,
+        hipLaunchKernelGGL((k_sample<false, true>), g, b, 0, st, nodes, cells, dists,
                            sample_off, D, n_total, u, S, idx, x);
     else
-        hipLaunchKernelGGL((k_sample<false, false>), g, b, 0, st, nodes, table, dists,
+        hipLaunchKernelGGL((k_sample<false, false>), g, b, 0, st, nodes, cells, dists,
                            sample_off, D, n_total, u, S, idx, x);
     return hipGetLastError();
 }
 
-hipError_t launch_sample_2d(const Node *nodes, const int32_t *table, const Dist *dists,
+hipError_t launch_sample_2d(const Node *nodes, const Cell *cells, const Dist *dists,
                             int32_t D, int64_t n_total, const uint64_t *u2, int64_t S,
                             int32_t *rc, double *xy, hipStream_t st) {
     const dim3 g(grid_for(S)), b(256);
     if (xy)
-        hipLaunchKernelGGL((k_sample_2d<true>), g, b, 0, st, nodes, table, dists, D, n_total, u2,
+        hipLaunchKernelGGL((k_sample_2d<true>), g, b, 0, st, nodes, cells, dists, D, n_total, u2,
                            S, rc, xy);
     else
-        hipLaunchKernelGGL((k_sample_2d<false>), g, b, 0, st, nodes, table, dists, D, n_total,
+        hipLaunchKernelGGL((k_sample_2d<false>), g, b, 0, st, nodes, cells, dists, D, n_total,
                            u2, S, rc, xy);
     return hipGetLastError();
 }
 
-hipError_t launch_sample_bsearch(const Node *nodes, const int32_t *table, const Dist *dists,
+hipError_t launch_sample_bsearch(const Node *nodes, const Cell *cells, const Dist *dists,
                                  bool cutpoint, const uint64_t *u, int64_t S, int32_t *idx,
                                  double *x, hipStream_t st) {
     const dim3 g(grid_for(S)), b(256);
     if (cutpoint && x)
-        hipLaunchKernelGGL((k_sample_bsearch<true, true>), g, b, 0, st, nodes, table, dists, u,
+        hipLaunchKernelGGL((k_sample_bsearch<true, true>), g, b, 0, st, nodes, cells, dists, u,
                            S, idx, x);
     else if (cutpoint)
-        hipLaunchKernelGGL((k_sample_bsearch<true, false>), g, b, 0, st, nodes, table, dists, u,
+        hipLaunchKernelGGL((k_sample_bsearch<true, false>), g, b, 0, st, nodes, cells, dists, u,
                            S, idx, x);
     else if (x)
-        hipLaunchKernelGGL((k_sample_bsearch<false, true>), g, b, 0, st, nodes, table, dists, u,
+        hipLaunchKernelGGL((k_sample_bsearch<false, true>), g, b, 0, st, nodes, cells, dists, u,
                            S, idx, x);
     else
-        hipLaunchKernelGGL((k_sample_bsearch<false, false>), g, b, 0, st, nodes, table, dists,
+        hipLaunchKernelGGL((k_sample_bsearch<false, false>), g, b, 0, st, nodes, cells, dists,
                            u, S, idx, x);
     return hipGetLastError();
 }

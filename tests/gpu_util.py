@@ -64,8 +64,27 @@ def assert_samples(idx_gpu, x_gpu, idx_ref, x_ref):
         assert err.max() <= X_TOL, f"max |x - x_ref| = {err.max()}"
 
 
+def expected_cells(ref):
+    """The repeated keys and child each guide cell record must hold, derived
+    from the oracle forest (see the cell record in include/rtforest.h)."""
+    MAX = np.uint64(TWO64 - 1)
+    key, child, table, eo = ref.key, ref.child, ref.table.astype(np.int64), ref.elem_off
+    node = table >= 0
+    a = np.where(node, table, ~table)  # first node a, or covering leaf i
+    end = eo[np.searchsorted(eo, a, side="right")]
+    nxt_ok = (a + 1 < end)
+    nxt = np.where(nxt_ok, key[np.minimum(a + 1, key.size - 1)], MAX)
+    nxt = np.where(nxt == MAX, MAX, nxt)
+    prev = np.where(key[a] == 0, np.uint64(0), key[np.maximum(a - 1, 0)])
+    k0 = np.where(node, prev, key[a])
+    k1 = np.where(node, key[a], nxt)
+    k2 = np.where(node, nxt, np.uint64(0))
+    c1 = np.where(node, child[a, 1], table).astype(np.int32)
+    return np.stack([k0, k1, k2], axis=1).astype(np.uint64), c1
+
+
 def assert_forest(f, ref, what=""):
-    key, child, table, W = f.export()
+    key, child, table, W, (ckeys, cc1) = f.export(with_cells=True)
     assert np.array_equal(W, ref.W), f"{what} totals differ"
     bk = np.nonzero(key != ref.key)[0]
     assert bk.size == 0, f"{what} {bk.size} keys differ, first at {bk[:5]}"
@@ -74,3 +93,8 @@ def assert_forest(f, ref, what=""):
         f"gpu {child[bc[:3]].tolist()} ref {ref.child[bc[:3]].tolist()}"
     bt = np.nonzero(table != ref.table)[0]
     assert bt.size == 0, f"{what} {bt.size} table entries differ, first at {bt[:5]}"
+    ek, ec1 = expected_cells(ref)
+    bx = np.nonzero((ckeys != ek).any(axis=1) | (cc1 != ec1))[0]
+    assert bx.size == 0, f"{what} {bx.size} cell records differ, first at {bx[:5]}: " \
+        f"gpu {ckeys[bx[:2]].tolist()} {cc1[bx[:2]].tolist()} ref {ek[bx[:2]].tolist()} " \
+        f"{ec1[bx[:2]].tolist()}"
