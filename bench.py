@@ -38,9 +38,14 @@ def parse():
     p.add_argument("--log2n", type=int, default=24)
     p.add_argument("--log2s", type=int, default=26)
     p.add_argument("--kind", choices=["uniform", "zipf"], default="uniform")
+    p.add_argument("--cell-ratio", type=float, default=1.0,
+                   help="guide cells per weight (the benchmark workload uses m = n)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--profile", action="store_true",
                    help="few steps, no baselines (for rocprofv3 runs)")
+    p.add_argument("--config", choices=["h24", "c3", "c4", "c5"], default="h24",
+                   help="h24: the benchmark line; c3/c4/c5: the 2D map, the uneven batch and "
+                        "the differentiable workload (extra measurements)")
     return p.parse_args()
 
 
@@ -87,13 +92,16 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the forest of "
               "one distribution is built and sampled on a single device", file=sys.stderr)
         sys.exit(2)
+    if args.config != "h24":
+        {"c3": run_c3, "c4": run_c4, "c5": run_c5}[args.config](args)
+        return
     import torch
     import paper_1901_05423_amd as rtf
     from paper_1901_05423_amd import workloads as wl
 
     dev = torch.device("cuda:0")
     n, S = 1 << args.log2n, 1 << args.log2s
-    m = n
+    m = max(1, int(round(args.cell_ratio * n)))
     cid = wl.H24_UNIFORM if args.kind == "uniform" else wl.H24_ZIPF
     r = wl.rng(cid)
     v_h = wl.weights_uniform(r, n) if args.kind == "uniform" else wl.weights_zipf(r, n)
@@ -180,7 +188,7 @@ def main():
         "config": {
             "workload": f"H24-{args.kind}: one distribution of n=2^{args.log2n} "
                         f"{'uniform(0,1]' if args.kind == 'uniform' else 'Zipf(1.1) permuted'} "
-                        f"f32 weights quantised to u32, m=n guide cells, S=2^{args.log2s} u64 "
+                        f"f32 weights quantised to u32, m={args.cell_ratio:g}n guide cells, S=2^{args.log2s} u64 "
                         "uniforms -> int32 index + f64 position",
             "n": n, "m": m, "samples": S,
         },
@@ -237,6 +245,168 @@ def cpu_baseline(v_h, u_h, n, m):
                   f"2^{int(np.log2(S))} uniforms ({t_search:.2f} s), scaled to the full step",
         "oracle_forest_melem_s": n / t_forest / 1e6,
     }
+
+
+def event_time(fn, reps):
+    """Mean milliseconds of fn() over reps runs, HIP events on the current stream."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def common(metric, unit, value, ms, args, dtype, workload, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": {"workload": workload}}
+    out.update(extra)
+    return out
+
+
+def run_c4(args):
+    """10,000 uneven distributions: quantise + build + sample in one launch
+    sequence, eagerly and as one replayed graph, against one library call
+    sequence per distribution."""
+    import torch
+    import paper_1901_05423_amd as rtf
+    from paper_1901_05423_amd import workloads as wl
+    from paper_1901_05423_amd.plan import BatchedPlan
+    r = wl.rng(wl.C4_BATCHED)
+    v_h, eo_h, so_h = wl.batched_uneven(r)
+    u_h = wl.uniforms(r, int(so_h[-1]))
+    dev = torch.device("cuda:0")
+    v, u = torch.from_numpy(v_h).to(dev), torch.from_numpy(u_h).to(dev)
+    eo, so = torch.from_numpy(eo_h).to(dev), torch.from_numpy(so_h).to(dev)
+    n, S, D = int(eo_h[-1]), int(so_h[-1]), eo_h.size - 1
+    plan = BatchedPlan(eo, eo, so, n, n, S)
+    for _ in range(args.warmup):
+        plan.run(v, u)
+    plan.check()
+    t_eager = event_time(lambda: plan.run(v, u), args.steps)
+    g = plan.capture(v, u)
+    t_graph = event_time(g.replay, args.steps)
+    # per-distribution launches of the same library (one quantise, build and
+    # sample call sequence per distribution)
+    forests = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in range(D):
+        a, b = int(eo_h[d]), int(eo_h[d + 1])
+        q, _ = rtf.quantize(v[a:b])
+        f = rtf.build(q, b - a)
+        rtf.sample(f, u[int(so_h[d]):int(so_h[d + 1])])
+        forests.append(f)
+        if len(forests) > 64:
+            forests.pop(0)
+    torch.cuda.synchronize()
+    t_b3 = (time.perf_counter() - t0) * 1e3
+    res = common(METRIC, "samples/s", S / (t_graph * 1e-3), t_graph, args, "u64",
+                 f"C4: {D} distributions, sizes log-uniform in [16, 65536] (n_total={n}), "
+                 f"uniform or Pareto(1.2) weights, m_d=n_d, {S} uniforms (64 per 1k weights), "
+                 "quantise + build + sample with x",
+                 elements_per_s=n / (t_graph * 1e-3), ms_eager=t_eager, ms_graph=t_graph,
+                 ms_per_distribution_launches=t_b3,
+                 speedup_vs_per_distribution=t_b3 / t_graph)
+    print(json.dumps(res), flush=True)
+
+
+def run_c3(args):
+    """4096 x 4096 map: marginal + 4096 rows quantised and built as one batch,
+    2^27 (row, column) pairs with sub-pixel positions."""
+    import torch
+    import paper_1901_05423_amd as rtf
+    from paper_1901_05423_amd import workloads as wl
+    r = wl.rng(wl.C3_MAP_2D)
+    img, marg = wl.map_2d(r)
+    R, C = img.shape
+    v_h = np.concatenate([marg, img.ravel()])
+    eo_h = np.concatenate([[0, R], R + C * np.arange(1, R + 1)]).astype(np.int64)
+    pairs = 1 << 27
+    u_h = wl.uniforms(r, 2 * pairs)
+    dev = torch.device("cuda:0")
+    v, u2 = torch.from_numpy(v_h).to(dev), torch.from_numpy(u_h).to(dev)
+    eo = torch.from_numpy(eo_h).to(dev)
+    n = int(eo_h[-1])
+    q = torch.empty(n, dtype=torch.uint32, device=dev)
+    scale = torch.empty(R + 1, dtype=torch.float64, device=dev)
+    ws = torch.empty(rtf.lib().rtf_workspace_bytes_batched(R + 1, n, n), dtype=torch.uint8,
+                     device=dev)
+    rc = torch.empty(2 * pairs, dtype=torch.int32, device=dev)
+    xy = torch.empty(2 * pairs, dtype=torch.float64, device=dev)
+    st = {}
+
+    def build():
+        rtf.quantize(v, eo, out=(q, scale))
+        st["f"] = rtf.build_batched(q, eo, eo) if "f" not in st else _rebuild(st["f"])
+
+    def _rebuild(f):
+        import ctypes
+        rtf._check(rtf.lib().rtf_build_batched(rtf._ptr(q), rtf._ptr(eo), rtf._ptr(eo), R + 1, n,
+                                               n, rtf._ptr(f.ws), f.ws.numel(), rtf._stream(),
+                                               ctypes.byref(f.desc)), "rtf_build_batched")
+        return f
+
+    build()
+    torch.cuda.synchronize()
+    st["f"].check()
+    t_build = event_time(build, args.steps)
+    t_sample = event_time(lambda: rtf.sample_2d(st["f"], u2, out=(rc, xy)), args.steps)
+    ms = t_build + t_sample
+    res = common(METRIC, "pairs/s", pairs / (ms * 1e-3), ms, args, "u64",
+                 "C3: 4096x4096 log-normal(0,1.5) map + 8 hot spots (1e4, sigma 3 px); marginal + "
+                 "4096 rows quantised and built as one batch (m_d=n_d); 2^27 (row, col) pairs + "
+                 "sub-pixel positions",
+                 ms_build=t_build, ms_sample=t_sample,
+                 build_melem_s=n / (t_build * 1e-3) / 1e6,
+                 sample_only_pairs_s=pairs / (t_sample * 1e-3))
+    print(json.dumps(res), flush=True)
+
+
+def run_c5(args):
+    """256 distributions of 4096 softplus weights, 2^20 uniforms each: forward
+    (quantise + build + sample) and the adjoint of L = sum sin(7x)."""
+    import torch
+    import paper_1901_05423_amd as rtf
+    from paper_1901_05423_amd import workloads as wl
+    D, nd, per = 256, 4096, 1 << 20
+    r = wl.rng(wl.C5_DIFF)
+    z_h = wl.logits(r, D, nd)
+    u_h = wl.uniforms(r, D * per)
+    dev = torch.device("cuda:0")
+    z = torch.from_numpy(z_h).to(dev)
+    u = torch.from_numpy(u_h).to(dev)
+    eo = torch.arange(D + 1, dtype=torch.int64, device=dev) * nd
+    so = torch.arange(D + 1, dtype=torch.int64, device=dev) * per
+    v = torch.nn.functional.softplus(z).reshape(-1).contiguous()
+    from paper_1901_05423_amd.plan import BatchedPlan
+    plan = BatchedPlan(eo, eo, so, D * nd, D * nd, D * per)
+    plan.run(v, u)
+    plan.check()
+    f = plan
+    gx = 7.0 * torch.cos(7.0 * plan.x)
+    bws = torch.empty(rtf.lib().rtf_backward_workspace_bytes(D, D * nd), dtype=torch.uint8,
+                      device=dev)
+    forest = rtf.Forest(plan.ws, plan.desc, dev)
+
+    def bwd():
+        return rtf.backward(forest, u, plan.idx, gx, plan.scale, sample_off=so, ws=bws)
+
+    t_fwd = event_time(lambda: plan.run(v, u), args.steps)
+    t_bwd = event_time(bwd, args.steps)
+    S = D * per
+    res = common(METRIC, "samples/s", S / ((t_fwd + t_bwd) * 1e-3), t_fwd + t_bwd, args, "u64",
+                 "C5: 256 distributions x 4096 softplus(N(0,1)) weights, 2^20 uniforms each; "
+                 "forward quantise + build + sample with x, backward dL/dw of L = sum sin(7x)",
+                 ms_forward=t_fwd, ms_backward=t_bwd,
+                 forward_samples_s=S / (t_fwd * 1e-3), backward_samples_s=S / (t_bwd * 1e-3))
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

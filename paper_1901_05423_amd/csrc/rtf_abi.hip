@@ -86,11 +86,10 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     f.scratch = b + L.tsum;
     f.scratch_bytes = L.total - L.tsum;
 
-    hipError_t e = launch_copy_offsets(D > 1 ? elem_off : nullptr, D > 1 ? cell_off : nullptr,
-                                       f.elem_off, f.cell_off, D, n, m, f.status, st);
-    if (e != hipSuccess) return RTF_ERR_HIP;
     BuildArgs a;
     a.w = w;
+    a.src_elem_off = D > 1 ? elem_off : nullptr;
+    a.src_cell_off = D > 1 ? cell_off : nullptr;
     a.elem_off = f.elem_off;
     a.cell_off = f.cell_off;
     a.D = D;
@@ -106,8 +105,7 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     a.dist_local = reinterpret_cast<uint64_t *>(b + L.dloc);
     a.defer_count = reinterpret_cast<int32_t *>(b + L.dcnt);
     a.defer_items = reinterpret_cast<int64_t *>(b + L.ditems);
-    e = launch_build(a, st);
-    if (e != hipSuccess) return RTF_ERR_HIP;
+    if (launch_build(a, st) != hipSuccess) return RTF_ERR_HIP;
     *out = f;
     return RTF_OK;
 }

@@ -108,11 +108,18 @@ __device__ inline int level_between(const Leaf &a, const Leaf &b) {
     return level_of(a.key, b.key);
 }
 
+// cell of a key: floor(key * m / 2^64), a shift when m is a power of two
+__device__ inline int32_t cell_of_key(uint64_t key, const Dist &P) {
+    const uint32_t sh = P.flags >> DIST_SHIFT_BIT;
+    const uint64_t c = sh ? (key >> sh) : mulhi64(key, (uint64_t)P.m);
+    return (int32_t)(P.co + (int64_t)c);
+}
+
 __device__ inline Leaf make_leaf(uint64_t C, const Dist &P) {
     Leaf L;
     if (C < P.W) {
         L.key = fixed_point_key(C, P.W << P.s, P.v, P.s);
-        L.cell = (int32_t)(P.co + (int64_t)mulhi64(L.key, (uint64_t)P.m));
+        L.cell = cell_of_key(L.key, P);
     } else {
         L.key = ~0ull;
         L.cell = -1;
@@ -152,23 +159,6 @@ __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// k_offsets
-// ---------------------------------------------------------------------------
-__global__ void k_offsets(const int64_t *src_e, const int64_t *src_c, int64_t *dst_e,
-                          int64_t *dst_c, int32_t D, int64_t n, int64_t m, uint32_t *status) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) *status = 0u;
-    if (t > D) return;
-    if (src_e) {
-        dst_e[t] = src_e[t];
-        dst_c[t] = src_c[t];
-    } else {  // one distribution
-        dst_e[t] = t ? n : 0;
-        dst_c[t] = t ? m : 0;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // k_tile_sums: the prefix-sum pass over the weights (Sec. 2.6 notes that the
 // prefix sum of an inversion method computes efficiently in parallel)
 // ---------------------------------------------------------------------------
@@ -177,6 +167,14 @@ __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
     __shared__ uint64_t s_wave[BT / 64];
     __shared__ uint64_t s_thr[BT];
     const int64_t t = blockIdx.x;
+    if (t == 0) {
+        // this build's status word and the offsets every later kernel reads
+        if (threadIdx.x == 0) *a.status = 0u;
+        for (int64_t q = threadIdx.x; q <= a.D; q += BT) {
+            a.elem_off[q] = BATCHED ? a.src_elem_off[q] : (q ? a.n_total : 0);
+            a.cell_off[q] = BATCHED ? a.src_cell_off[q] : (q ? a.m_total : 0);
+        }
+    }
     const int64_t base = t * TILE;
     const int64_t i0 = base + (int64_t)threadIdx.x * ITEMS;
     uint32_t r[ITEMS];
@@ -197,13 +195,13 @@ __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
         int32_t lo = 0, hi = a.D;  // first d with elem_off[d] >= base
         while (lo < hi) {
             int32_t mid = (lo + hi) >> 1;
-            if (a.elem_off[mid] < base) lo = mid + 1;
+            if (a.src_elem_off[mid] < base) lo = mid + 1;
             else hi = mid;
         }
         dlo = lo;
     }
     for (int32_t d = dlo + threadIdx.x; d < a.D; d += BT) {
-        int64_t e = a.elem_off[d];
+        int64_t e = a.src_elem_off[d];
         if (e >= end) break;
         int64_t off = e - base;
         int64_t tq = off / ITEMS;
@@ -223,17 +221,37 @@ template <bool BATCHED>
 __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
     __shared__ uint64_t s_wave[PT / 64];
     const int64_t nt = a.ntiles;
-    const int64_t per = (nt + PT - 1) / PT;
-    const int64_t lo = (int64_t)threadIdx.x * per;
-    const int64_t hi = lo + per < nt ? lo + per : nt;
-    uint64_t sum = 0;
-    for (int64_t q = lo; q < hi; ++q) sum += a.tile_sum[q];
-    uint64_t total;
-    uint64_t run = block_excl_scan<PT / 64>(sum, s_wave, total);
-    for (int64_t q = lo; q < hi; ++q) {
-        a.tile_prefix[q] = run;
-        run += a.tile_sum[q];
+    // rounds of PT x 8 tile sums; thread t scans 8 consecutive ones
+    constexpr int CH = 8;
+    uint64_t carry = 0;
+    for (int64_t r0 = 0; r0 < nt; r0 += (int64_t)PT * CH) {
+        const int64_t lo = r0 + (int64_t)threadIdx.x * CH;
+        uint64_t v[CH];
+        if (lo + CH <= nt) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(a.tile_sum + lo);
+#pragma unroll
+            for (int q = 0; q < CH / 2; ++q) {
+                const uint4 x = p[q];
+                v[2 * q] = ((uint64_t)x.y << 32) | x.x;
+                v[2 * q + 1] = ((uint64_t)x.w << 32) | x.z;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < CH; ++q) v[q] = (lo + q < nt) ? a.tile_sum[lo + q] : 0;
+        }
+        uint64_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < CH; ++q) sum += v[q];
+        uint64_t round_total;
+        uint64_t run = carry + block_excl_scan<PT / 64>(sum, s_wave, round_total);
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            if (lo + q < nt) a.tile_prefix[lo + q] = run;
+            run += v[q];
+        }
+        carry += round_total;
     }
+    const uint64_t total = carry;
     __threadfence_block();
     __syncthreads();
     for (int32_t d = threadIdx.x; d < a.D; d += PT) {
@@ -260,6 +278,8 @@ __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
             P.s = (uint32_t)clz64(P.W);
             P.v = reciprocal_2by1(P.W << P.s);
         }
+        if (P.m > 1 && (P.m & (P.m - 1)) == 0)
+            P.flags |= (uint32_t)(64 - __builtin_ctzll((uint64_t)P.m)) << DIST_SHIFT_BIT;
         a.dists[d] = P;
     }
 }
@@ -269,18 +289,42 @@ __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
 //
 // Phase 1 (thread t owns ITEMS consecutive leaves): prefix sums, keys and
 // cells into LDS, plus HALO leaves on either side of the tile.  Phase 2: the
-// levels of all boundaries held.  Phase 3 (node j = base + t + BT*k): the
-// node records and guide-table entries, so that each wave stores 64
-// consecutive 16-byte records (1 KiB) per instruction.
+// levels of all boundaries held.  Phase 3: parent links.  Alg. 1 merges a
+// subtree across whichever of its two outside boundaries has the lower level
+// (the left one on a tie); so the subtree rooted at boundary b, which spans
+// the leaves between L = the nearest boundary left of b with a higher level
+// and R = the nearest boundary right of b with a level at least as high, is
+// child 0 of node R+1 when lvl(L) > lvl(R) and child 1 of node L+1
+// otherwise; a leaf is the same with L, R its two adjacent boundaries.  Every
+// boundary and leaf of the window writes itself into its parent's child slot
+// in LDS; the nearest-higher searches read eight levels per LDS access.
+// Phase 4: node records, 64 consecutive 16-byte records per wave store, and
+// the guide cells into an LDS window.  Phase 5: the guide cell records, 64
+// consecutive 32-byte records per wave.  A node with an empty child slot (its
+// child lies outside the window) is finished by the fix-up kernel.  Indices
+// inside the tile are 32-bit: local leaf li is global leaf lb0 + li, local
+// boundary bi lies between local leaves bi and bi + 1 (it is node bi + 1).
 // ---------------------------------------------------------------------------
-constexpr int LEAF_N = TILE + 2 * HALO;  // leaves base-HALO .. base+TILE+HALO-1
-constexpr int LVL_N = LEAF_N - 1;        // boundaries base-HALO .. base+TILE+HALO-2
+constexpr int LEAF_N = TILE + 2 * HALO;
+constexpr int LVL_N = LEAF_N - 1;  // real boundaries; lvl[LVL_N] is padding
+static_assert(LEAF_N % 8 == 0, "levels are read 8 at a time");
+constexpr int32_t SLOT_EMPTY = INT32_MIN;  // never a node or leaf reference
+
+// Owner codes of the guide cells staged in the window: which local leaf a
+// cell record comes from and how.
+constexpr int32_t WIN_EMPTY = -1;
+constexpr int32_t WIN_ROOT = 0 << 16;  // the cell's first node
+constexpr int32_t WIN_HEAD = 1 << 16;  // covered by the leaf before that node
+constexpr int32_t WIN_TAIL = 2 << 16;  // covered by a distribution's last leaf
 
 struct TileSmem {
     uint64_t key[LEAF_N];
     int32_t cell[LEAF_N];
-    uint8_t lvl[LVL_N + 1];
+    int32_t slot[2 * TILE];  // child slots of the tile's own nodes
+    int32_t win[WIN];        // owner codes of cells c_begin .. c_begin + WIN - 1
+    uint64_t lvl8[LEAF_N / 8];
     uint64_t wave[BT / 64];
+    int64_t c_begin;
     int32_t ndefer;
     int64_t items[DEFER_CAP];
 };
@@ -290,47 +334,73 @@ __device__ inline void push_item(TileSmem &sm, int64_t item) {
     if (k < DEFER_CAP) sm.items[k] = item;
 }
 
-// Left child of the node at boundary k with level l: the root of leaves
-// [L+1, k], where L is the nearest boundary left of k with a level above l.
-// Scanning leftwards, the first maximum met is the rightmost one.
-__device__ inline bool scan_left(const uint8_t *lvl, int64_t lb0, int64_t k, int l,
-                                 int32_t &ref) {
-    int64_t b = k - 1;
-    int best = -1;
-    int64_t bestb = -1;
-    for (int steps = 0;; ++steps) {
-        if (b < lb0 || steps >= SCAN_CAP) return false;
-        int lb = lvl[b - lb0];
-        if (lb > l) break;
-        if (lb > best) {
-            best = lb;
-            bestb = b;
-        }
-        --b;
-    }
-    ref = (best < 0) ? ~(int32_t)k : (int32_t)(bestb + 1);
-    return true;
+__device__ inline int lvl_at(const TileSmem &sm, int bi) {
+    return (int)((sm.lvl8[bi >> 3] >> (8 * (bi & 7))) & 0xff);
 }
 
-// Right child: the root of leaves [k1, R], R the nearest boundary at or right
-// of k1 with a level >= l.  Scanning rightwards, ties move to the right.
-__device__ inline bool scan_right(const uint8_t *lvl, int64_t lb0, int64_t lb1, int64_t k1,
-                                  int l, int32_t &ref) {
-    int64_t b = k1;
-    int best = -1;
-    int64_t bestb = -1;
-    for (int steps = 0;; ++steps) {
-        if (b > lb1 || steps >= SCAN_CAP) return false;
-        int lb = lvl[b - lb0];
-        if (lb >= l) break;
-        if (lb >= best) {
-            best = lb;
-            bestb = b;
-        }
-        ++b;
+// bit 7 of every byte of w (eight levels, each < 128) that is >= t
+__device__ inline uint64_t ge_mask(uint64_t w, int t) {
+    const uint64_t ones = 0x0101010101010101ull;
+    return (w + (uint64_t)(128 - t) * ones) & (0x80ull * ones);
+}
+
+constexpr int SCAN_WORDS = SCAN_CAP / 8;
+
+// nearest boundary at or left of bi with a level >= t, or -1
+__device__ inline int nearest_ge_left(const TileSmem &sm, int bi, int t) {
+    if (bi < 0) return -1;
+    int wi = bi >> 3;
+    const int pos = bi & 7;
+    uint64_t m = ge_mask(sm.lvl8[wi], t);
+    if (pos < 7) m &= (1ull << (8 * pos + 8)) - 1;
+    for (int steps = 0; m == 0; ++steps) {
+        if (--wi < 0 || steps >= SCAN_WORDS) return -1;
+        m = ge_mask(sm.lvl8[wi], t);
     }
-    ref = (best < 0) ? ~(int32_t)k1 : (int32_t)(bestb + 1);
-    return true;
+    return wi * 8 + (63 - clz64(m)) / 8;
+}
+
+// nearest boundary at or right of bi with a level >= t, or -1
+__device__ inline int nearest_ge_right(const TileSmem &sm, int bi, int t) {
+    if (bi >= LVL_N) return -1;
+    int wi = bi >> 3;
+    uint64_t m = ge_mask(sm.lvl8[wi], t) & (~0ull << (8 * (bi & 7)));
+    for (int steps = 0; m == 0; ++steps) {
+        if (++wi >= LEAF_N / 8 || steps >= SCAN_WORDS) return -1;
+        m = ge_mask(sm.lvl8[wi], t);
+    }
+    const int r = wi * 8 + __builtin_ctzll(m) / 8;
+    return r < LVL_N ? r : -1;
+}
+
+// write ref into child slot `side` of local node pn if the tile owns it
+__device__ inline void link(TileSmem &sm, int pn, int side, int32_t ref) {
+    const int s = pn - HALO;
+    if (s >= 0 && s < TILE) sm.slot[2 * s + side] = ref;
+}
+
+// stage the record of cell c (owner code w) in the window, or store it
+// directly when the cell lies past the window
+__device__ inline void put_cell(TileSmem &sm, Cell *cells, int64_t c, int32_t w, int32_t lb0) {
+    const int64_t x = c - sm.c_begin;
+    if (x >= 0 && x < WIN) {
+        sm.win[x] = w;
+        return;
+    }
+    const int li = w & 0xffff;
+    const int32_t g = lb0 + li;
+    if ((w & ~0xffff) == WIN_HEAD) store_cell(cells, c, sm.key[li - 1], sm.key[li], 0, ~(g - 1), ~(g - 1));
+    else store_cell(cells, c, sm.key[li], KEY_END, 0, ~g, ~g);  // WIN_TAIL
+}
+
+__device__ inline void root_cell_record(const TileSmem &sm, Cell *cells, int64_t c, int li,
+                                        int32_t lb0) {
+    const uint64_t kj = sm.key[li];
+    const int32_t cj = sm.cell[li], nc = sm.cell[li + 1];
+    const uint64_t nk = sm.key[li + 1];
+    const bool next_same = nc >= 0 && !(nk == 0 && nc != cj);
+    store_cell(cells, c, kj == 0 ? 0 : sm.key[li - 1], kj, next_same ? nk : KEY_END, lb0 + li,
+               sm.slot[2 * (li - HALO) + 1]);
 }
 
 template <bool BATCHED>
@@ -340,13 +410,13 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     const int64_t t = blockIdx.x;
     const int64_t base = t * TILE;
     const int64_t n = a.n_total;
-    const int64_t lb0 = base - HALO;             // lowest boundary (and leaf) held
-    const int64_t lb1 = base + TILE + HALO - 2;  // highest boundary held
+    const int32_t lb0 = (int32_t)(base - HALO);  // global index of local leaf 0
     if (tid == 0) sm.ndefer = 0;
 
     // ---- phase 1: keys and cells of the tile's leaves -----------------------
     {
         const int64_t i0 = base + (int64_t)tid * ITEMS;
+        const int li0 = HALO + tid * ITEMS;
         uint32_t wv[ITEMS];
         load_items(a.w, i0, n, vec, wv);
         uint64_t sum = 0;
@@ -359,15 +429,15 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
         if (BATCHED) dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
         Dist P = a.dists[dcur];
         int64_t dend = P.eo + P.n;
+        const int live = (int)(n - i0 < ITEMS ? (n - i0 > 0 ? n - i0 : 0) : ITEMS);
 #pragma unroll
         for (int e = 0; e < ITEMS; ++e) {
-            const int64_t i = i0 + e;
             Leaf L;
             L.key = 0;
             L.cell = -2;
-            if (i < n) {
+            if (e < live) {
                 if (BATCHED) {
-                    while (i >= dend) {
+                    while (i0 + e >= dend) {
                         ++dcur;
                         P = a.dists[dcur];
                         dend = P.eo + P.n;
@@ -375,8 +445,8 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
                 }
                 L = make_leaf(G - P.G0, P);
             }
-            sm.key[i - lb0] = L.key;
-            sm.cell[i - lb0] = L.cell;
+            sm.key[li0 + e] = L.key;
+            sm.cell[li0 + e] = L.cell;
             G += wv[e];
         }
         // halo leaves: lanes 0..31 of wave 0 the HALO leaves left of the tile,
@@ -403,62 +473,116 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     }
     __syncthreads();
 
-    // ---- phase 2: levels of all boundaries held ----------------------------
-    for (int b = tid; b < LVL_N; b += BT) {
-        Leaf A{sm.key[b], sm.cell[b]};
-        Leaf B{sm.key[b + 1], sm.cell[b + 1]};
-        sm.lvl[b] = (uint8_t)level_between(A, B);
+    // ---- phase 2: levels of all boundaries held; empty slots and window ----
+    for (int w8 = tid; w8 < LEAF_N / 8; w8 += BT) {
+        uint64_t word = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int bi = 8 * w8 + q;
+            int l = SENT;  // the padding byte past the last boundary
+            if (bi < LVL_N) {
+                Leaf A{sm.key[bi], sm.cell[bi]};
+                Leaf B{sm.key[bi + 1], sm.cell[bi + 1]};
+                l = level_between(A, B);
+            }
+            word |= (uint64_t)l << (8 * q);
+        }
+        sm.lvl8[w8] = word;
+    }
+    for (int x = tid; x < 2 * TILE; x += BT) sm.slot[x] = SLOT_EMPTY;
+    for (int x = tid; x < WIN; x += BT) sm.win[x] = WIN_EMPTY;
+    if (tid == 0) {
+        // first guide cell whose record comes from a leaf of this tile
+        const int32_t c = sm.cell[HALO], cp = sm.cell[HALO - 1];
+        int64_t cb;
+        if (c >= 0) {
+            const bool dist_start = cp < 0 || (sm.key[HALO] == 0 && cp != c);
+            cb = dist_start ? c : (int64_t)cp + 1;
+        } else {  // the tile starts past its distribution's last positive weight
+            const Dist &P = a.dists[BATCHED ? find_segment(a.elem_off, a.D, base) : 0];
+            cb = P.co + P.m;
+        }
+        sm.c_begin = cb;
     }
     __syncthreads();
 
-    // ---- phase 3: node records and guide-table entries ----------------------
-#pragma unroll 2
-    for (int k = 0; k < ITEMS; ++k) {
-        const int64_t j = base + tid + (int64_t)BT * k;
-        if (j >= n) break;
-        const int64_t lj = j - lb0;
-        const uint64_t kj = sm.key[lj];
-        const int32_t cj = sm.cell[lj];
-        int32_t c0 = ~(int32_t)j, c1 = ~(int32_t)j;
-        bool ok = true;
+    // ---- phase 3: parent links ---------------------------------------------
+    // internal nodes: boundaries of the window below SENT
+    for (int bi = tid; bi < LVL_N; bi += BT) {
+        const int l = lvl_at(sm, bi);
+        if (l >= SENT) continue;
+        const int L = nearest_ge_left(sm, bi - 1, l + 1);
+        const int R = nearest_ge_right(sm, bi + 1, l);
+        if (L < 0 || R < 0) continue;  // the parent is found by the fix-up
+        const int32_t ref = lb0 + bi + 1;
+        if (lvl_at(sm, L) > lvl_at(sm, R)) link(sm, R + 1, 0, ref);
+        else link(sm, L + 1, 1, ref);
+    }
+    // leaves that may hang from the tile's nodes
+    for (int li = HALO - 1 + tid; li < HALO + TILE; li += BT) {
+        if (sm.cell[li] < 0) continue;
+        const int ll = lvl_at(sm, li - 1), lr = lvl_at(sm, li);
+        const int32_t ref = ~(lb0 + li);
+        if (ll > lr) link(sm, li + 1, 0, ref);
+        else link(sm, li, 1, ref);
+    }
+    __syncthreads();
+
+    // ---- phase 4: node records; guide cells into the window ----------------
+    const int live_nodes = (int)(n - base < TILE ? n - base : TILE);
+    for (int jl = tid; jl < live_nodes; jl += BT) {
+        const int li = HALO + jl;
+        const int32_t gj = lb0 + li;  // global node / leaf index
+        const uint64_t kj = sm.key[li];
+        const int32_t cj = sm.cell[li];
+        int32_t c0 = ~gj, c1 = ~gj;
         if (cj >= 0) {
-            const int l = sm.lvl[lj - 1];  // boundary j-1
-            // leaf j+1 carries mass and belongs to j's distribution
-            const int32_t nc = sm.cell[lj + 1];
-            const uint64_t nk = sm.key[lj + 1];
-            const bool next_same = nc >= 0 && !(nk == 0 && nc != cj);
-            if (l == SENT) {
-                // first node of a cell: child 1 roots the cell's tree, child 0
-                // is the interval overlapping the cell from the left
-                const uint64_t kp = sm.key[lj - 1];
-                c0 = (kj == 0) ? ~(int32_t)j : ~(int32_t)(j - 1);
-                ok = scan_right(sm.lvl, lb0, lb1, j, SENT, c1);
-                store_cell(a.cells, cj, kj == 0 ? 0 : kp, kj, next_same ? nk : KEY_END,
-                           (int32_t)j, c1);
-                const int32_t pc = sm.cell[lj - 1];
+            const bool root = lvl_at(sm, li - 1) == SENT;
+            c0 = root ? ((kj == 0) ? ~gj : ~(gj - 1)) : sm.slot[2 * jl];
+            c1 = sm.slot[2 * jl + 1];
+            if (c0 == SLOT_EMPTY || c1 == SLOT_EMPTY) push_item(sm, ((int64_t)gj << 2) | ITEM_NODE);
+            // leaf gj+1 carries mass and belongs to gj's distribution
+            const int32_t nc = sm.cell[li + 1];
+            const bool next_same = nc >= 0 && !(sm.key[li + 1] == 0 && nc != cj);
+            if (root) {
+                const int64_t x = cj - sm.c_begin;
+                if (x >= 0 && x < WIN) sm.win[x] = WIN_ROOT | li;
+                else root_cell_record(sm, a.cells, cj, li, lb0);
+                const int32_t pc = sm.cell[li - 1];
                 if (kj != 0 && cj - pc > 1) {
-                    if (cj - pc - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_HEAD);
-                    else fill_run(a.cells, pc + 1, cj, (int32_t)(j - 1), kp, kj);
+                    if (cj - pc - 1 > RUN_CAP) push_item(sm, ((int64_t)gj << 2) | ITEM_HEAD);
+                    else
+                        for (int64_t c = pc + 1; c < cj; ++c) put_cell(sm, a.cells, c, WIN_HEAD | li, lb0);
                 }
-            } else {
-                ok = scan_left(sm.lvl, lb0, j - 1, l, c0);
-                ok = ok && scan_right(sm.lvl, lb0, lb1, j, l, c1);
             }
             // the distribution's last leaf with mass covers the remaining cells
             if (!next_same) {
-                const Dist &P = a.dists[BATCHED ? find_segment(a.elem_off, a.D, j) : 0];
+                const Dist &P = a.dists[BATCHED ? find_segment(a.elem_off, a.D, gj) : 0];
                 const int64_t cend = P.co + P.m;
                 if (cend - cj > 1) {
-                    if (cend - cj - 1 > RUN_CAP) push_item(sm, (j << 2) | ITEM_TAIL);
-                    else fill_run(a.cells, cj + 1, cend, (int32_t)j, kj, KEY_END);
+                    if (cend - cj - 1 > RUN_CAP) push_item(sm, ((int64_t)gj << 2) | ITEM_TAIL);
+                    else
+                        for (int64_t c = cj + 1; c < cend; ++c) put_cell(sm, a.cells, c, WIN_TAIL | li, lb0);
                 }
             }
         }
-        if (!ok) push_item(sm, (j << 2) | ITEM_NODE);
         // a deferred node's children are rewritten by the fix-up kernel
-        store_node(a.nodes, j, kj, c0, c1);
+        store_node(a.nodes, gj, kj, c0, c1);
     }
     __syncthreads();
+
+    // ---- phase 5: the staged guide cells, 64 consecutive records per wave ---
+    for (int x = tid; x < WIN; x += BT) {
+        const int32_t w = sm.win[x];
+        if (w == WIN_EMPTY) continue;
+        const int64_t c = sm.c_begin + x;
+        const int li = w & 0xffff;
+        const int32_t g = lb0 + li;
+        const int32_t kind = w & ~0xffff;
+        if (kind == WIN_ROOT) root_cell_record(sm, a.cells, c, li, lb0);
+        else if (kind == WIN_HEAD) store_cell(a.cells, c, sm.key[li - 1], sm.key[li], 0, ~(g - 1), ~(g - 1));
+        else store_cell(a.cells, c, sm.key[li], KEY_END, 0, ~g, ~g);
+    }
     const int32_t nd = sm.ndefer;
     if (tid == 0) a.defer_count[t] = nd;
     const int32_t nk = nd < DEFER_CAP ? nd : DEFER_CAP;
@@ -485,8 +609,7 @@ struct GlobalView {
             L.cell = -1;
             return L;
         }
-        const Dist &P = a.dists[dist_of(i)];
-        L.cell = (int32_t)(P.co + (int64_t)mulhi64(L.key, (uint64_t)P.m));
+        L.cell = cell_of_key(L.key, a.dists[dist_of(i)]);
         return L;
     }
     __device__ int level(int64_t b) const { return level_between(leaf(b), leaf(b + 1)); }
@@ -610,13 +733,27 @@ struct GlobalView {
 };
 
 template <bool BATCHED>
+__device__ void fixup_tile(const BuildArgs &a, int64_t t, int64_t *s_item, int32_t &s_nrun,
+                           uint64_t *s_run);
+
+// Grid-stride over tiles: most tiles defer nothing, so a few hundred blocks
+// that skip them quickly cost less than one block per tile.
+template <bool BATCHED>
 __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
     __shared__ int64_t s_item[DEFER_CAP];
     __shared__ int32_t s_nrun;
     __shared__ uint64_t s_run[5];
-    const int64_t t = blockIdx.x;
+    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        if (a.defer_count[t] == 0) continue;  // uniform across the block
+        fixup_tile<BATCHED>(a, t, s_item, s_nrun, s_run);
+        __syncthreads();
+    }
+}
+
+template <bool BATCHED>
+__device__ void fixup_tile(const BuildArgs &a, int64_t t, int64_t *s_item, int32_t &s_nrun,
+                           uint64_t *s_run) {
     const int32_t cnt = a.defer_count[t];
-    if (cnt == 0) return;
     GlobalView<BATCHED> gv(a);
     const int64_t base = t * TILE;
     if (cnt > DEFER_CAP) {
@@ -675,29 +812,20 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_copy_offsets(const int64_t *src_e, const int64_t *src_c, int64_t *dst_e,
-                               int64_t *dst_c, int32_t D, int64_t n, int64_t m,
-                               uint32_t *status, hipStream_t st) {
-    int64_t cnt = (int64_t)D + 1;
-    int blocks = (int)((cnt + 255) / 256);
-    hipLaunchKernelGGL(k_offsets, dim3(blocks), dim3(256), 0, st, src_e, src_c, dst_e, dst_c,
-                       D, n, m, status);
-    return hipGetLastError();
-}
-
 hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
     const bool vec = (reinterpret_cast<uintptr_t>(a.w) & 15) == 0;
     const dim3 grid((unsigned)a.ntiles);
+    const dim3 fixgrid((unsigned)(a.ntiles < 512 ? a.ntiles : 512));
     if (a.D > 1) {
         hipLaunchKernelGGL(k_tile_sums<true>, grid, dim3(BT), 0, st, a, vec);
         hipLaunchKernelGGL(k_dist_params<true>, dim3(1), dim3(PT), 0, st, a);
         hipLaunchKernelGGL(k_build_tile<true>, grid, dim3(BT), 0, st, a, vec);
-        hipLaunchKernelGGL(k_fixup<true>, grid, dim3(BT), 0, st, a);
+        hipLaunchKernelGGL(k_fixup<true>, fixgrid, dim3(BT), 0, st, a);
     } else {
         hipLaunchKernelGGL(k_tile_sums<false>, grid, dim3(BT), 0, st, a, vec);
         hipLaunchKernelGGL(k_dist_params<false>, dim3(1), dim3(PT), 0, st, a);
         hipLaunchKernelGGL(k_build_tile<false>, grid, dim3(BT), 0, st, a, vec);
-        hipLaunchKernelGGL(k_fixup<false>, grid, dim3(BT), 0, st, a);
+        hipLaunchKernelGGL(k_fixup<false>, fixgrid, dim3(BT), 0, st, a);
     }
     return hipGetLastError();
 }

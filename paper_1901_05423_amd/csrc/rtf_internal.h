@@ -13,10 +13,12 @@ namespace rtf {
 // weights that carry mass (Alg. 1 sets the neighbour "to the maximum").
 constexpr int SENT = 65;
 
-// Build tile: 512 threads x 8 consecutive elements.
+// Build tile: 512 threads x 4 consecutive elements.
 constexpr int BT = 512;
-constexpr int ITEMS = 8;
+constexpr int ITEMS = 4;
 constexpr int TILE = BT * ITEMS;
+// Guide cells staged in LDS per tile before their coalesced store.
+constexpr int WIN = 2 * TILE;
 // Leaves on either side of a tile whose keys are recomputed locally so that
 // subtree scans near the tile edges stay in LDS.
 constexpr int HALO = 32;
@@ -25,7 +27,7 @@ constexpr int SCAN_CAP = 64;
 // Longest guide-table run written by one lane; longer ones go to the fix-up.
 constexpr int RUN_CAP = 64;
 // Deferred items kept per tile; more make the fix-up redo the whole tile.
-constexpr int DEFER_CAP = 512;
+constexpr int DEFER_CAP = 128;
 
 // deferred item kinds (low 2 bits of an item)
 constexpr int64_t ITEM_NODE = 0;  // node record j
@@ -64,14 +66,18 @@ struct alignas(64) Dist {
     uint32_t flags;
 };
 constexpr uint32_t DIST_ZERO = 1u;
+// bits 8..15 of Dist::flags: 64 - log2(m) when m is a power of two >= 2, else 0
+constexpr int DIST_SHIFT_BIT = 8;
 
 // status word bits: 1 << rtf_status
 __host__ __device__ inline uint32_t status_bit(int code) { return 1u << code; }
 
 struct BuildArgs {
     const uint32_t *w;
-    const int64_t *elem_off;  // workspace copy, D+1
-    const int64_t *cell_off;  // workspace copy, D+1
+    const int64_t *src_elem_off;  // the caller's offsets (null for one distribution)
+    const int64_t *src_cell_off;
+    int64_t *elem_off;            // workspace copy, D+1
+    int64_t *cell_off;            // workspace copy, D+1
     int32_t D;
     int64_t n_total;
     int64_t m_total;
@@ -150,9 +156,6 @@ hipError_t launch_sample_2d(const Node *nodes, const Cell *cells, const Dist *di
 hipError_t launch_sample_bsearch(const Node *nodes, const Cell *cells,
                                  const Dist *dists, bool cutpoint, const uint64_t *u,
                                  int64_t S, int32_t *idx, double *x, hipStream_t st);
-hipError_t launch_copy_offsets(const int64_t *src_e, const int64_t *src_c, int64_t *dst_e,
-                               int64_t *dst_c, int32_t D, int64_t n, int64_t m,
-                               uint32_t *status, hipStream_t st);
 hipError_t launch_quantize(const float *v, const int64_t *elem_off, int32_t D,
                            int64_t n_total, uint32_t *out, double *scale,
                            uint32_t *status, hipStream_t st);

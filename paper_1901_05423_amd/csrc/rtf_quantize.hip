@@ -104,6 +104,54 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
     }
 }
 
+// One distribution: a fixed grid strides over the weights with 16-byte
+// loads, so only a few thousand blocks reach the atomic.
+constexpr int QMAX_BLOCKS = 2048;
+__global__ __launch_bounds__(QT) void k_qmax_single(const float *__restrict__ v, int64_t n,
+                                                    bool vec, double *scale, uint32_t *status) {
+    __shared__ uint32_t s_max[QT / 64];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    uint32_t mx = 0;
+    bool bad = false;
+    auto take = [&](float x) {
+        if (!(x >= 0.0f) || isinf(x)) {
+            bad = true;
+            return;
+        }
+        const uint32_t b = __float_as_uint(x);
+        mx = b > mx ? b : mx;
+    };
+    const int64_t stride = (int64_t)gridDim.x * QT;
+    const int64_t n4 = vec ? n / 4 : 0;
+    const float4 *v4 = reinterpret_cast<const float4 *>(v);
+    for (int64_t i = (int64_t)blockIdx.x * QT + threadIdx.x; i < n4; i += stride) {
+        const float4 x = v4[i];
+        take(x.x);
+        take(x.y);
+        take(x.z);
+        take(x.w);
+    }
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * QT + threadIdx.x; i < n; i += stride) take(v[i]);
+    if (bad) s_bad = 1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_down(mx, o, 64);
+        mx = y > mx ? y : mx;
+    }
+    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = 0;
+        for (int w = 0; w < QT / 64; ++w) m = s_max[w] > m ? s_max[w] : m;
+        const uint32_t seen = __hip_atomic_load(max_word(scale, 0), __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        if (m > seen) atomicMax(max_word(scale, 0), m);
+        if (s_bad && status) atomicOr(status, status_bit(RTF_ERR_VALUE));
+    }
+}
+
 __device__ inline double scale_of(const double *scale, int32_t d) {
     const float mx = __uint_as_float(*reinterpret_cast<const uint32_t *>(scale + d));
     return mx > 0.0f ? 4294967295.0 / (double)mx : 0.0;
@@ -155,8 +203,15 @@ hipError_t launch_quantize(const float *v, const int64_t *elem_off, int32_t D, i
     const int db = (D + 255) / 256;
     const int64_t nb = (n_total + (int64_t)QT * QI - 1) / ((int64_t)QT * QI);
     hipLaunchKernelGGL(k_qinit, dim3(db), dim3(256), 0, st, scale, D);
-    hipLaunchKernelGGL(k_qmax, dim3((unsigned)nb), dim3(QT), 0, st, v, elem_off, D, n_total,
-                       scale, status);
+    if (elem_off) {
+        hipLaunchKernelGGL(k_qmax, dim3((unsigned)nb), dim3(QT), 0, st, v, elem_off, D, n_total,
+                           scale, status);
+    } else {
+        const int64_t g = nb < QMAX_BLOCKS ? nb : QMAX_BLOCKS;
+        const bool vec = (reinterpret_cast<uintptr_t>(v) & 15) == 0;
+        hipLaunchKernelGGL(k_qmax_single, dim3((unsigned)g), dim3(QT), 0, st, v, n_total, vec,
+                           scale, status);
+    }
     hipLaunchKernelGGL(k_qapply, dim3((unsigned)nb), dim3(QT), 0, st, v, elem_off, D, n_total,
                        scale, out);
     hipLaunchKernelGGL(k_qfinal, dim3(db), dim3(256), 0, st, scale, D);

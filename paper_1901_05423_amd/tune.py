@@ -1,0 +1,103 @@
+"""Autotuner for the guide-table size.
+
+The sampled indices do not depend on the number of guide cells m; only speed
+does.  The paper leaves m open ("as much memory as affordable, or
+proportional to n", Sec. 3).  More cells let more samples finish in one
+cell record, but a larger table costs build bytes and cache capacity.
+`best_cell_ratio` times build + sample for candidate ratios m/n on the
+caller's own data and shape, and remembers the winner in a JSON cache keyed
+by the device architecture and the size bucket (log2 of n and of S/n).
+
+Environment: RTF_CELL_RATIO forces a ratio; RTF_TUNE_CACHE names the cache
+file (default ~/.cache/rtforest/tune.json).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+CANDIDATES = (0.25, 0.5, 1.0, 2.0)
+
+
+def cache_path() -> str:
+    return os.environ.get("RTF_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "rtforest", "tune.json"))
+
+
+def bucket_key(arch: str, op: str, n: int, samples: int) -> str:
+    ln = int(round(math.log2(max(n, 1))))
+    ls = int(round(math.log2(max(samples, 1) / max(n, 1)))) if samples else -99
+    return f"{arch}|{op}|n2^{ln}|s/n2^{ls}"
+
+
+def load_cache(path: str | None = None) -> dict:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store_cache(entries: dict, path: str | None = None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(entries, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def forced_ratio():
+    v = os.environ.get("RTF_CELL_RATIO")
+    return float(v) if v else None
+
+
+def device_arch() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def _time_ms(fn, reps=5):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def best_cell_ratio(w, u, candidates=CANDIDATES, use_cache=True, reps=5) -> float:
+    """Cell ratio m/n with the fastest build + sample for uint32 weights `w`
+    (one distribution) and uniforms `u`, both device tensors."""
+    forced = forced_ratio()
+    if forced is not None:
+        return forced
+    from . import build, sample
+    key = bucket_key(device_arch(), "single", w.numel(), u.numel())
+    cache = load_cache() if use_cache else {}
+    if key in cache:
+        return float(cache[key]["ratio"])
+    n = w.numel()
+    times = {}
+    for r in candidates:
+        m = max(1, int(round(r * n)))
+        holder = {}
+
+        def step():
+            holder["f"] = build(w, m)
+            sample(holder["f"], u)
+
+        times[r] = _time_ms(step, reps)
+    best = min(times, key=times.get)
+    if use_cache:
+        cache[key] = {"ratio": best, "ms": {str(k): v for k, v in times.items()}}
+        store_cache(cache)
+    return best

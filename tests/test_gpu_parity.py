@@ -215,3 +215,43 @@ def test_h24_full_size(rtf, orc, kind):
     i_ref, x_ref = orc.search(q_ref, u)
     assert_samples(idx.cpu().numpy(), x.cpu().numpy(), i_ref, x_ref)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_shapes(rtf, orc, seed):
+    """Random sizes, guide sizes and zero patterns against the oracle."""
+    rng = np.random.default_rng(9000 + seed)
+    n = int(rng.choice([rng.integers(1, 300), rng.integers(300, 9000),
+                        rng.integers(9000, 120000)]))
+    ratio = float(rng.choice([0.01, 0.3, 1.0, 1.0, 2.5]))
+    m = max(1, int(n * ratio))
+    zf = float(rng.choice([0.0, 0.0, 0.2, 0.7, 0.97]))
+    note(f"random seed={seed} n={n} m={m} zeros={zf}")
+    w = random_weights(rng, n, zero_frac=zf, skew=bool(seed % 2))
+    if seed % 5 == 4:
+        w[-int(rng.integers(1, n + 1)):] = 0
+        if w.sum() == 0:
+            w[0] = 7
+    build_and_compare(rtf, orc, w, m, S_extra=5000, seed=seed, baselines=seed % 3 == 0)
+
+
+def test_single_tree_large(rtf, orc):
+    """m = 1 and m = 2: one or two trees over 300k leaves, so most nodes'
+    subtrees leave their tile and the fix-up kernel finishes them."""
+    note("single tree n=300000")
+    rng = np.random.default_rng(31)
+    w = random_weights(rng, 300000, skew=True)
+    build_and_compare(rtf, orc, w, 1, S_extra=50000, seed=1)
+    build_and_compare(rtf, orc, w, 2, S_extra=50000, seed=2)
+
+
+def test_deferral_overflow(rtf, orc):
+    """Long runs of equal keys (zero weights) inside one cell make every node
+    of a tile defer, which overflows the per-tile list."""
+    note("deferral overflow n=40000")
+    rng = np.random.default_rng(32)
+    w = random_weights(rng, 40000)
+    for a in range(1000, 40000, 5000):
+        w[a:a + 3000] = 0
+    build_and_compare(rtf, orc, w, 4, S_extra=20000, seed=3)
+    build_and_compare(rtf, orc, w, 40000, S_extra=20000, seed=4)
