@@ -15,7 +15,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace layout of a forest of D distributions, n_total leaves, m_total cells.
 struct Layout {
-    size_t status, nodes, cells, dists, eoff, coff, tsum, tpre, dloc, dcnt, ditems, total;
+    size_t status, nodes, cells, dists, eoff, coff, tsum, tpre, dloc, dcnt, ditems, runs, total;
     int64_t ntiles;
 };
 
@@ -44,7 +44,9 @@ Layout make_layout(int32_t D, int64_t n, int64_t m) {
     L.dcnt = o;
     o = align256(o + sizeof(int32_t) * (size_t)L.ntiles);
     L.ditems = o;
-    o = align256(o + sizeof(int64_t) * (size_t)L.ntiles * DEFER_CAP);
+    o = align256(o + sizeof(int32_t) * (size_t)L.ntiles * DEFER_CAP);
+    L.runs = o;
+    o = align256(o + sizeof(RunChunk) * (size_t)run_chunk_cap(m));
     L.total = o;
     return L;
 }
@@ -104,7 +106,9 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     a.tile_prefix = reinterpret_cast<uint64_t *>(b + L.tpre);
     a.dist_local = reinterpret_cast<uint64_t *>(b + L.dloc);
     a.defer_count = reinterpret_cast<int32_t *>(b + L.dcnt);
-    a.defer_items = reinterpret_cast<int64_t *>(b + L.ditems);
+    a.defer_items = reinterpret_cast<int32_t *>(b + L.ditems);
+    a.run_count = reinterpret_cast<int32_t *>(b + L.status + 64);  // in the status block
+    a.runs = reinterpret_cast<RunChunk *>(b + L.runs);
     if (launch_build(a, st) != hipSuccess) return RTF_ERR_HIP;
     *out = f;
     return RTF_OK;

@@ -80,15 +80,22 @@ __device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i)
 
 __device__ inline void load_items(const uint32_t *w, int64_t i0, int64_t n, bool vec,
                                   uint32_t *r) {
+    static_assert(ITEMS == 2 || ITEMS % 4 == 0, "vector loads of 8 or 16 bytes");
     if (vec && i0 + ITEMS <= n) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(w + i0);
+        if constexpr (ITEMS == 2) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(w + i0);
+            r[0] = v.x;
+            r[1] = v.y;
+        } else {
+            const uint4 *p = reinterpret_cast<const uint4 *>(w + i0);
 #pragma unroll
-        for (int q = 0; q < ITEMS / 4; ++q) {
-            uint4 v = p[q];
-            r[4 * q + 0] = v.x;
-            r[4 * q + 1] = v.y;
-            r[4 * q + 2] = v.z;
-            r[4 * q + 3] = v.w;
+            for (int q = 0; q < ITEMS / 4; ++q) {
+                uint4 v = p[q];
+                r[4 * q + 0] = v.x;
+                r[4 * q + 1] = v.y;
+                r[4 * q + 2] = v.z;
+                r[4 * q + 3] = v.w;
+            }
         }
     } else {
 #pragma unroll
@@ -143,10 +150,27 @@ __device__ inline void store_cell(Cell *cells, int64_t g, uint64_t k0, uint64_t 
     p[1] = b;
 }
 
-// cells [c_lo, c_hi) covered by interval i alone, whose keys are lo and hi
-__device__ inline void fill_run(Cell *cells, int64_t c_lo, int64_t c_hi, int32_t i, uint64_t lo,
-                                uint64_t hi) {
-    for (int64_t c = c_lo; c < c_hi; ++c) store_cell(cells, c, lo, hi, 0, ~i, ~i);
+// List the guide-table run [lo, hi), covered by interval i with keys k0 and
+// k1, in chunks of FILL_CH cells for the fix-up kernel.
+__device__ inline void push_run(const BuildArgs &a, int64_t lo, int64_t hi, int32_t i, uint64_t k0,
+                                uint64_t k1) {
+    const int32_t nch = (int32_t)((hi - lo + FILL_CH - 1) / FILL_CH);
+    const int32_t first = atomicAdd(a.run_count, nch);
+    const int64_t cap = run_chunk_cap(a.m_total);
+    for (int32_t q = 0; q < nch; ++q) {
+        if (first + q >= cap) {  // impossible by the bound of run_chunk_cap
+            atomicOr(a.status, status_bit(RTF_ERR_WORKSPACE));
+            return;
+        }
+        RunChunk r;
+        r.k0 = k0;
+        r.k1 = k1;
+        r.lo = (int32_t)(lo + (int64_t)q * FILL_CH);
+        r.hi = (int32_t)(hi < lo + (int64_t)(q + 1) * FILL_CH ? hi : lo + (int64_t)(q + 1) * FILL_CH);
+        r.i = i;
+        r.pad = 0;
+        a.runs[first + q] = r;
+    }
 }
 
 __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t c0, int32_t c1) {
@@ -169,7 +193,10 @@ __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
     const int64_t t = blockIdx.x;
     if (t == 0) {
         // this build's status word and the offsets every later kernel reads
-        if (threadIdx.x == 0) *a.status = 0u;
+        if (threadIdx.x == 0) {
+            *a.status = 0u;
+            *a.run_count = 0;
+        }
         for (int64_t q = threadIdx.x; q <= a.D; q += BT) {
             a.elem_off[q] = BATCHED ? a.src_elem_off[q] : (q ? a.n_total : 0);
             a.cell_off[q] = BATCHED ? a.src_cell_off[q] : (q ? a.m_total : 0);
@@ -308,6 +335,8 @@ __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
 constexpr int LEAF_N = TILE + 2 * HALO;
 constexpr int LVL_N = LEAF_N - 1;  // real boundaries; lvl[LVL_N] is padding
 static_assert(LEAF_N % 8 == 0, "levels are read 8 at a time");
+static_assert(2 * HALO == 64, "wave 0 loads both halos, one leaf per lane");
+static_assert(WIN % 4 == 0 && (LEAF_N * 12) % 16 == 0, "16-byte clears of slot and window");
 constexpr int32_t SLOT_EMPTY = INT32_MIN;  // never a node or leaf reference
 
 // Owner codes of the guide cells staged in the window: which local leaf a
@@ -317,7 +346,7 @@ constexpr int32_t WIN_ROOT = 0 << 16;  // the cell's first node
 constexpr int32_t WIN_HEAD = 1 << 16;  // covered by the leaf before that node
 constexpr int32_t WIN_TAIL = 2 << 16;  // covered by a distribution's last leaf
 
-struct TileSmem {
+struct alignas(16) TileSmem {
     uint64_t key[LEAF_N];
     int32_t cell[LEAF_N];
     int32_t slot[2 * TILE];  // child slots of the tile's own nodes
@@ -326,10 +355,10 @@ struct TileSmem {
     uint64_t wave[BT / 64];
     int64_t c_begin;
     int32_t ndefer;
-    int64_t items[DEFER_CAP];
+    int32_t items[DEFER_CAP];
 };
 
-__device__ inline void push_item(TileSmem &sm, int64_t item) {
+__device__ inline void push_item(TileSmem &sm, int32_t item) {
     int32_t k = atomicAdd(&sm.ndefer, 1);
     if (k < DEFER_CAP) sm.items[k] = item;
 }
@@ -414,20 +443,35 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     if (tid == 0) sm.ndefer = 0;
 
     // ---- phase 1: keys and cells of the tile's leaves -----------------------
+    // Every global load of the phase (weights, halo weights, tile prefix,
+    // distribution parameters) is issued before the block scan, so a block
+    // waits for one round trip instead of three.
     {
         const int64_t i0 = base + (int64_t)tid * ITEMS;
         const int li0 = HALO + tid * ITEMS;
         uint32_t wv[ITEMS];
         load_items(a.w, i0, n, vec, wv);
+        const uint64_t tp = a.tile_prefix[t];
+        int32_t dcur = 0;
+        if (BATCHED) dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
+        Dist P = a.dists[dcur];
+        // halo leaves: lanes 0..HALO-1 of wave 0 the HALO leaves left of the
+        // tile, lanes HALO..63 the HALO leaves right of it
+        const bool left = tid < HALO;
+        const int64_t hi_ = left ? base - HALO + tid : base + TILE + (tid - HALO);
+        const bool hexists = tid < 64 && hi_ >= 0 && hi_ < n;
+        uint64_t hw = 0;
+        Dist HP;
+        if (tid < 64) {
+            hw = hexists ? a.w[hi_] : 0u;
+            HP = a.dists[(BATCHED && hexists) ? find_segment(a.elem_off, a.D, hi_) : 0];
+        }
+
         uint64_t sum = 0;
 #pragma unroll
         for (int e = 0; e < ITEMS; ++e) sum += wv[e];
         uint64_t tile_total;
-        const uint64_t tp = a.tile_prefix[t];
         uint64_t G = tp + block_excl_scan<BT / 64>(sum, sm.wave, tile_total);
-        int32_t dcur = 0;
-        if (BATCHED) dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
-        Dist P = a.dists[dcur];
         int64_t dend = P.eo + P.n;
         const int live = (int)(n - i0 < ITEMS ? (n - i0 > 0 ? n - i0 : 0) : ITEMS);
 #pragma unroll
@@ -449,22 +493,15 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
             sm.cell[li0 + e] = L.cell;
             G += wv[e];
         }
-        // halo leaves: lanes 0..31 of wave 0 the HALO leaves left of the tile,
-        // lanes 32..63 the HALO leaves right of it
         if (tid < 64) {
-            const bool left = tid < HALO;
-            const int64_t i = left ? base - HALO + tid : base + TILE + (tid - HALO);
-            const bool exists = i >= 0 && i < n;
-            uint64_t wi = exists ? a.w[i] : 0u;
-            uint64_t suf = wave_incl_suffix(left ? wi : 0);
-            uint64_t pre = wave_incl_scan(left ? 0 : wi);
+            const uint64_t suf = wave_incl_suffix(left ? hw : 0);
+            const uint64_t pre = wave_incl_scan(left ? 0 : hw);
             Leaf L;
             L.key = 0;
             L.cell = -2;
-            if (exists) {
-                uint64_t Gi = left ? tp - suf : tp + tile_total + pre - wi;
-                int32_t d = BATCHED ? find_segment(a.elem_off, a.D, i) : 0;
-                L = make_leaf(Gi - a.dists[d].G0, a.dists[d]);
+            if (hexists) {
+                const uint64_t Gi = left ? tp - suf : tp + tile_total + pre - hw;
+                L = make_leaf(Gi - HP.G0, HP);
             }
             const int slot = left ? tid : TILE + tid;
             sm.key[slot] = L.key;
@@ -474,23 +511,23 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     __syncthreads();
 
     // ---- phase 2: levels of all boundaries held; empty slots and window ----
-    for (int w8 = tid; w8 < LEAF_N / 8; w8 += BT) {
-        uint64_t word = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int bi = 8 * w8 + q;
+    {
+        // one level per thread and byte (consecutive lanes, no bank conflicts);
+        // byte bi of the array is byte bi & 7 of word bi >> 3
+        uint8_t *lv = reinterpret_cast<uint8_t *>(sm.lvl8);
+        for (int bi = tid; bi < LEAF_N; bi += BT) {
             int l = SENT;  // the padding byte past the last boundary
-            if (bi < LVL_N) {
-                Leaf A{sm.key[bi], sm.cell[bi]};
-                Leaf B{sm.key[bi + 1], sm.cell[bi + 1]};
-                l = level_between(A, B);
-            }
-            word |= (uint64_t)l << (8 * q);
+            if (bi < LVL_N)
+                l = level_between(Leaf{sm.key[bi], sm.cell[bi]}, Leaf{sm.key[bi + 1], sm.cell[bi + 1]});
+            lv[bi] = (uint8_t)l;
         }
-        sm.lvl8[w8] = word;
     }
-    for (int x = tid; x < 2 * TILE; x += BT) sm.slot[x] = SLOT_EMPTY;
-    for (int x = tid; x < WIN; x += BT) sm.win[x] = WIN_EMPTY;
+    {
+        const int4 se = make_int4(SLOT_EMPTY, SLOT_EMPTY, SLOT_EMPTY, SLOT_EMPTY);
+        const int4 we = make_int4(WIN_EMPTY, WIN_EMPTY, WIN_EMPTY, WIN_EMPTY);
+        for (int x = tid; x < 2 * TILE / 4; x += BT) reinterpret_cast<int4 *>(sm.slot)[x] = se;
+        for (int x = tid; x < WIN / 4; x += BT) reinterpret_cast<int4 *>(sm.win)[x] = we;
+    }
     if (tid == 0) {
         // first guide cell whose record comes from a leaf of this tile
         const int32_t c = sm.cell[HALO], cp = sm.cell[HALO - 1];
@@ -540,7 +577,7 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
             const bool root = lvl_at(sm, li - 1) == SENT;
             c0 = root ? ((kj == 0) ? ~gj : ~(gj - 1)) : sm.slot[2 * jl];
             c1 = sm.slot[2 * jl + 1];
-            if (c0 == SLOT_EMPTY || c1 == SLOT_EMPTY) push_item(sm, ((int64_t)gj << 2) | ITEM_NODE);
+            if (c0 == SLOT_EMPTY || c1 == SLOT_EMPTY) push_item(sm, gj);
             // leaf gj+1 carries mass and belongs to gj's distribution
             const int32_t nc = sm.cell[li + 1];
             const bool next_same = nc >= 0 && !(sm.key[li + 1] == 0 && nc != cj);
@@ -550,7 +587,7 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
                 else root_cell_record(sm, a.cells, cj, li, lb0);
                 const int32_t pc = sm.cell[li - 1];
                 if (kj != 0 && cj - pc > 1) {
-                    if (cj - pc - 1 > RUN_CAP) push_item(sm, ((int64_t)gj << 2) | ITEM_HEAD);
+                    if (cj - pc - 1 > RUN_CAP) push_run(a, pc + 1, cj, gj - 1, sm.key[li - 1], kj);
                     else
                         for (int64_t c = pc + 1; c < cj; ++c) put_cell(sm, a.cells, c, WIN_HEAD | li, lb0);
                 }
@@ -560,7 +597,7 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
                 const Dist &P = a.dists[BATCHED ? find_segment(a.elem_off, a.D, gj) : 0];
                 const int64_t cend = P.co + P.m;
                 if (cend - cj > 1) {
-                    if (cend - cj - 1 > RUN_CAP) push_item(sm, ((int64_t)gj << 2) | ITEM_TAIL);
+                    if (cend - cj - 1 > RUN_CAP) push_run(a, cj + 1, cend, gj, kj, KEY_END);
                     else
                         for (int64_t c = cj + 1; c < cend; ++c) put_cell(sm, a.cells, c, WIN_TAIL | li, lb0);
                 }
@@ -705,107 +742,42 @@ struct GlobalView {
         store_cell(a.cells, Lj.cell, k0, Lj.key, next_same(Lj, Ln) ? Ln.key : KEY_END,
                    (int32_t)j, c1);
     }
-    // guide-table runs owned by node / leaf j: cells [lo, hi) covered by
-    // interval i with keys k0, k1
-    __device__ bool head_run(int64_t j, int64_t &lo, int64_t &hi, int32_t &i, uint64_t &k0,
-                             uint64_t &k1) const {
-        Leaf Lj = leaf(j), Lp = leaf(j - 1);
-        if (Lj.cell < 0 || Lj.key == 0 || level_between(Lp, Lj) != SENT) return false;
-        lo = (int64_t)Lp.cell + 1;
-        hi = Lj.cell;
-        i = (int32_t)(j - 1);
-        k0 = Lp.key;
-        k1 = Lj.key;
-        return hi > lo;
-    }
-    __device__ bool tail_run(int64_t j, int64_t &lo, int64_t &hi, int32_t &i, uint64_t &k0,
-                             uint64_t &k1) const {
-        Leaf Lj = leaf(j), Ln = leaf(j + 1);
-        if (Lj.cell < 0 || next_same(Lj, Ln)) return false;
-        const Dist &P = a.dists[dist_of(j)];
-        lo = (int64_t)Lj.cell + 1;
-        hi = P.co + P.m;
-        i = (int32_t)j;
-        k0 = Lj.key;
-        k1 = KEY_END;
-        return hi > lo;
-    }
 };
 
 template <bool BATCHED>
-__device__ void fixup_tile(const BuildArgs &a, int64_t t, int64_t *s_item, int32_t &s_nrun,
-                           uint64_t *s_run);
+__device__ void fixup_tile(const BuildArgs &a, int64_t t);
 
 // Grid-stride over tiles: most tiles defer nothing, so a few hundred blocks
-// that skip them quickly cost less than one block per tile.
+// that skip them quickly cost less than one block per tile.  Then all blocks
+// fill the listed guide-table run chunks, one chunk per block at a time.
 template <bool BATCHED>
 __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
-    __shared__ int64_t s_item[DEFER_CAP];
-    __shared__ int32_t s_nrun;
-    __shared__ uint64_t s_run[5];
     for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         if (a.defer_count[t] == 0) continue;  // uniform across the block
-        fixup_tile<BATCHED>(a, t, s_item, s_nrun, s_run);
-        __syncthreads();
+        fixup_tile<BATCHED>(a, t);
+    }
+    const int64_t cap = run_chunk_cap(a.m_total);
+    const int64_t nrun = *a.run_count < cap ? *a.run_count : cap;
+    for (int64_t k = blockIdx.x; k < nrun; k += gridDim.x) {
+        const RunChunk r = a.runs[k];
+        for (int64_t c = r.lo + threadIdx.x; c < r.hi; c += BT) store_cell(a.cells, c, r.k0, r.k1, 0, ~r.i, ~r.i);
     }
 }
 
 template <bool BATCHED>
-__device__ void fixup_tile(const BuildArgs &a, int64_t t, int64_t *s_item, int32_t &s_nrun,
-                           uint64_t *s_run) {
+__device__ void fixup_tile(const BuildArgs &a, int64_t t) {
     const int32_t cnt = a.defer_count[t];
     GlobalView<BATCHED> gv(a);
     const int64_t base = t * TILE;
-    if (cnt > DEFER_CAP) {
-        // too many deferrals: redo every node and table run of the tile
-        for (int64_t j = base + threadIdx.x; j < base + TILE && j < a.n_total; j += BT) {
-            uint64_t kj;
-            int32_t c0, c1;
-            if (gv.node(j, kj, c0, c1)) gv.root_cell(j, c1);
-            store_node(a.nodes, j, kj, c0, c1);
-            int64_t lo, hi;
-            int32_t i;
-            uint64_t k0, k1;
-            if (gv.head_run(j, lo, hi, i, k0, k1)) fill_run(a.cells, lo, hi, i, k0, k1);
-            if (gv.tail_run(j, lo, hi, i, k0, k1)) fill_run(a.cells, lo, hi, i, k0, k1);
-        }
-        return;
-    }
-    if (threadIdx.x == 0) s_nrun = 0;
-    __syncthreads();
-    for (int32_t k = threadIdx.x; k < cnt; k += BT) {
-        int64_t it = a.defer_items[t * DEFER_CAP + k];
-        int64_t j = it >> 2;
-        if ((it & 3) == ITEM_NODE) {
-            uint64_t kj;
-            int32_t c0, c1;
-            if (gv.node(j, kj, c0, c1)) gv.root_cell(j, c1);
-            store_node(a.nodes, j, kj, c0, c1);
-        } else {
-            s_item[atomicAdd(&s_nrun, 1)] = it;
-        }
-    }
-    __syncthreads();
-    const int32_t nr = s_nrun;
-    for (int32_t r = 0; r < nr; ++r) {
-        if (threadIdx.x == 0) {
-            int64_t it = s_item[r], lo = 0, hi = 0;
-            int32_t i = 0;
-            uint64_t k0 = 0, k1 = 0;
-            bool has = ((it & 3) == ITEM_HEAD) ? gv.head_run(it >> 2, lo, hi, i, k0, k1)
-                                               : gv.tail_run(it >> 2, lo, hi, i, k0, k1);
-            s_run[0] = has ? (uint64_t)lo : 0;
-            s_run[1] = has ? (uint64_t)hi : 0;
-            s_run[2] = (uint64_t)(uint32_t)i;
-            s_run[3] = k0;
-            s_run[4] = k1;
-        }
-        __syncthreads();
-        const int64_t lo = (int64_t)s_run[0], hi = (int64_t)s_run[1];
-        const int32_t i = (int32_t)(uint32_t)s_run[2];
-        const uint64_t k0 = s_run[3], k1 = s_run[4];
-        for (int64_t c = lo + threadIdx.x; c < hi; c += BT) store_cell(a.cells, c, k0, k1, 0, ~i, ~i);
-        __syncthreads();
+    // more deferrals than were kept: redo every node record of the tile
+    const bool all = cnt > DEFER_CAP;
+    const int64_t count = all ? (a.n_total - base < TILE ? a.n_total - base : TILE) : cnt;
+    for (int64_t k = threadIdx.x; k < count; k += BT) {
+        const int64_t j = all ? base + k : (int64_t)a.defer_items[t * DEFER_CAP + k];
+        uint64_t kj;
+        int32_t c0, c1;
+        if (gv.node(j, kj, c0, c1)) gv.root_cell(j, c1);
+        store_node(a.nodes, j, kj, c0, c1);
     }
 }
 

@@ -17,22 +17,21 @@ constexpr int SENT = 65;
 constexpr int BT = 512;
 constexpr int ITEMS = 4;
 constexpr int TILE = BT * ITEMS;
-// Guide cells staged in LDS per tile before their coalesced store.
-constexpr int WIN = 2 * TILE;
+// Guide cells staged in LDS per tile before their coalesced store.  With m
+// proportional to n a tile's records fall in about m/n * TILE consecutive
+// cells; records past the window are stored directly.
+constexpr int WIN = TILE + 128;
 // Leaves on either side of a tile whose keys are recomputed locally so that
 // subtree scans near the tile edges stay in LDS.
 constexpr int HALO = 32;
 // Longest in-LDS subtree scan; longer ones are finished by the fix-up kernel.
 constexpr int SCAN_CAP = 64;
-// Longest guide-table run written by one lane; longer ones go to the fix-up.
+// Longest guide-table run written by one lane; a longer run is listed in
+// chunks of FILL_CH cells that all blocks of the fix-up kernel fill together.
 constexpr int RUN_CAP = 64;
-// Deferred items kept per tile; more make the fix-up redo the whole tile.
+constexpr int FILL_CH = 4096;
+// Deferred node records kept per tile; more make the fix-up redo the tile.
 constexpr int DEFER_CAP = 128;
-
-// deferred item kinds (low 2 bits of an item)
-constexpr int64_t ITEM_NODE = 0;  // node record j
-constexpr int64_t ITEM_HEAD = 1;  // empty cells before cell-start leaf j
-constexpr int64_t ITEM_TAIL = 2;  // empty cells after the last leaf j
 
 struct alignas(16) Node {
     uint64_t key;
@@ -52,6 +51,20 @@ struct alignas(32) Cell {
     int32_t ref, c1;
 };
 constexpr uint64_t KEY_END = ~0ull;
+
+// A chunk of a guide-table run: cells [lo, hi) are all covered by interval i,
+// whose keys are k0 and k1.
+struct alignas(16) RunChunk {
+    uint64_t k0, k1;
+    int32_t lo, hi, i, pad;
+};
+
+// Capacity of the chunk list for m cells.  Runs longer than RUN_CAP cells are
+// disjoint, so there are at most m / (RUN_CAP + 1) of them, and a run of L
+// cells has ceil(L / FILL_CH) <= L / FILL_CH + 1 chunks.
+__host__ __device__ inline int64_t run_chunk_cap(int64_t m) {
+    return m / FILL_CH + m / (RUN_CAP + 1) + 2;
+}
 
 // Per-distribution parameters, written by the build's scan kernel.
 struct alignas(64) Dist {
@@ -90,7 +103,9 @@ struct BuildArgs {
     uint64_t *tile_prefix;  // [ntiles]
     uint64_t *dist_local;   // [D]: in-tile prefix at each distribution start
     int32_t *defer_count;   // [ntiles]
-    int64_t *defer_items;   // [ntiles * DEFER_CAP]
+    int32_t *defer_items;   // [ntiles * DEFER_CAP]: deferred node indices
+    int32_t *run_count;     // chunks listed in runs
+    RunChunk *runs;         // [run_chunk_cap(m_total)]
 };
 
 // ---- exact 64-bit fixed-point helpers ----------------------------------
