@@ -4,7 +4,9 @@
 One step = the whole hot path over one batch held in HBM:
     quantise f32 weights -> build guide table + radix tree forest -> sample
     2^26 uniforms to indices and continuous positions x.
-Workload H24: n = 2^24 uniform(0,1] weights, m = n guide cells, S = 2^26.
+Workload H24: n = 2^24 uniform(0,1] weights, S = 2^26; the number of guide
+cells m is the autotuner's choice among m/n in {1/4, 1/2, 1, 2} (timed on the
+same data before the measured steps; --cell-ratio fixes it instead).
 
 Prints one JSON line (the last line of stdout).  ``value`` is samples per
 second of the whole step; build Melem/s, sampling-only samples/s and the two
@@ -27,7 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = ("samples/s + build Melem/s at n=2^24 (% HBM peak) vs binary search, bit-exact")
 HBM_PEAK_GBS = 8000.0
-NODE_B, CELL_B, U_B, IDX_B, X_B, W_B = 16, 32, 8, 4, 8, 4
+NODE_B, CELL_B, U_B, IDX_B, X_B, W_B = 16, 64, 8, 4, 8, 4
 
 
 def parse():
@@ -38,8 +40,9 @@ def parse():
     p.add_argument("--log2n", type=int, default=24)
     p.add_argument("--log2s", type=int, default=26)
     p.add_argument("--kind", choices=["uniform", "zipf"], default="uniform")
-    p.add_argument("--cell-ratio", type=float, default=1.0,
-                   help="guide cells per weight (the benchmark workload uses m = n)")
+    p.add_argument("--cell-ratio", type=float, default=None,
+                   help="guide cells per weight m/n; default: the autotuner's choice for "
+                        "this shape (tune.best_cell_ratio, timed on the same data)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--profile", action="store_true",
                    help="few steps, no baselines (for rocprofv3 runs)")
@@ -49,19 +52,18 @@ def parse():
     return p.parse_args()
 
 
-def sample_bytes_model(key, child, table, m, u):
-    """Replay Alg. 2 on the host (exported forest, subsample of the uniforms)
-    and return the mean algorithmic bytes a sample reads beyond its streams:
-    the 32-byte cell record, plus 16 bytes per node record of the descent and
-    32 bytes for the two keys of the position when the cell record alone does
-    not resolve the sample; also the mean descent length and the fraction of
-    samples resolved by the cell record."""
+def sample_bytes_model(key, child, table, K, aux, m, u):
+    """Replay Alg. 2 with the cell records on the host (exported forest,
+    subsample of the uniforms) and return the mean algorithmic bytes a sample
+    reads beyond its streams: the 64-byte cell record, plus 16 bytes per node
+    record of the descent and 32 bytes for the two keys of the position when
+    the record does not resolve the sample; also the mean descent length and
+    the fraction of samples the record resolves."""
     g = ((u.astype(object) * m) >> 64).astype(np.int64)
     ref = table[g].astype(np.int64)
-    deeper = (ref >= 0)
-    a = np.where(deeper, ref, 0)
-    deeper &= (u >= key[a]) & (child[a, 1] >= 0)
-    j = np.where(deeper, child[a, 1], -1).astype(np.int64)
+    ax = aux[g].astype(np.int64)
+    deeper = (ref >= 0) & (ax >= 0) & (u >= K[g, 6])
+    j = np.where(deeper, ax, -1).astype(np.int64)
     visits = np.zeros(u.size, np.int64)
     active = j >= 0
     while active.any():
@@ -101,7 +103,6 @@ def main():
 
     dev = torch.device("cuda:0")
     n, S = 1 << args.log2n, 1 << args.log2s
-    m = max(1, int(round(args.cell_ratio * n)))
     cid = wl.H24_UNIFORM if args.kind == "uniform" else wl.H24_ZIPF
     r = wl.rng(cid)
     v_h = wl.weights_uniform(r, n) if args.kind == "uniform" else wl.weights_zipf(r, n)
@@ -110,6 +111,16 @@ def main():
     u = torch.from_numpy(u_h).to(dev)
     q = torch.empty(n, dtype=torch.uint32, device=dev)
     scale = torch.empty(1, dtype=torch.float64, device=dev)
+    tune_info = {"source": "fixed"}
+    if args.cell_ratio is None:
+        # the guide size m/n is the autotuner's choice, timed on this data
+        from paper_1901_05423_amd import tune
+        rtf.quantize(v, out=(q, scale))
+        ratio, times = tune.best_cell_ratio(q, u, use_cache=False, with_times=True)
+        tune_info = {"source": "tuner", "ms_build_plus_sample": times}
+    else:
+        ratio = args.cell_ratio
+    m = max(1, int(round(ratio * n)))
     idx = torch.empty(S, dtype=torch.int32, device=dev)
     x = torch.empty(S, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
@@ -165,9 +176,9 @@ def main():
     # algorithmic bytes per sample of the sampling kernel: stream u, idx, x;
     # one guide entry; the node records the descent reads; the two keys the
     # position reads (one record pair)
-    key, child, table, W = f.export()
+    key, child, table, W, (K, aux) = f.export(with_cells=True)
     sub = u_h[:: max(1, S // (1 << 20))]
-    extra, dbar, resolved = sample_bytes_model(key, child, table, m, sub)
+    extra, dbar, resolved = sample_bytes_model(key, child, table, K, aux, m, sub)
     per_sample = U_B + IDX_B + X_B + extra
     sample_bytes = per_sample * S
     build_bytes = (W_B + NODE_B) * n + CELL_B * m
@@ -188,9 +199,9 @@ def main():
         "config": {
             "workload": f"H24-{args.kind}: one distribution of n=2^{args.log2n} "
                         f"{'uniform(0,1]' if args.kind == 'uniform' else 'Zipf(1.1) permuted'} "
-                        f"f32 weights quantised to u32, m={args.cell_ratio:g}n guide cells, S=2^{args.log2s} u64 "
-                        "uniforms -> int32 index + f64 position",
-            "n": n, "m": m, "samples": S,
+                        f"f32 weights quantised to u32, m={ratio:g}n guide cells ({tune_info['source']}), "
+                        f"S=2^{args.log2s} u64 uniforms -> int32 index + f64 position",
+            "n": n, "m": m, "samples": S, "cell_ratio": ratio, "cell_ratio_tuning": tune_info,
         },
         "phase_ms": {"quantize": t_quant, "build": t_build, "sample": t_sample},
         "build_melem_s": n / (t_build * 1e-3) / 1e6,

@@ -66,17 +66,26 @@ typedef enum rtf_status {
  * where node j splits between leaf j-1 and leaf j and compares against U_j
  * (Sec. 3.1).  A reference r >= 0 is a node, a reference r < 0 is leaf ~r.
  *
- * Guide table: m_total 32-byte cell records
- *   { uint64 k0, k1, k2; int32 ref; int32 c1; }.
+ * Guide table: m_total 64-byte cell records
+ *   { uint64 k[7]; int32 ref; int32 aux; }.
  * ref is the guide entry of Sec. 2.5 and 3.2: the first node a of cell g
  * (whose child 1 roots the cell's tree and whose child 0 is the interval
  * overlapping the cell from the left) or, for a cell that no lower bound falls
- * in, the complement ~i of the one leaf covering it.  The other fields repeat
- * keys and one child so that a sample whose cell holds at most one lower bound
- * needs this record only: for ref = a, k0 = U_{a-1} (0 at a distribution
- * start), k1 = U_a, k2 = U_{a+1}, c1 = child 1 of node a; for ref = ~i,
- * k0 = U_i, k1 = U_{i+1}, k2 = 0, c1 = ref.  A key of all ones stands for the
- * end of the distribution.
+ * in, the complement ~i of the one leaf covering it.  The keys repeat the
+ * bounds a sample of the cell compares against, so that most samples need
+ * this record only:
+ *   ref = ~i:  k[0] = U_i, k[1] = U_{i+1}, aux = ref;
+ *   ref = a, the cell holding c lower bounds U_a .. U_{a+c-1}:
+ *     k[0] = U_{a-1} (0 at a distribution start), k[t] = U_{a+t-1} for
+ *     t = 1 .. min(c+1, 6), so that k[c+1] = U_{a+c} is the upper end of the
+ *     cell's last interval when c <= 5;
+ *     c <= 5: aux = ~c and the sample is leaf a-1+j, j the number of
+ *     k[1..c] at or below u;
+ *     c > 5: aux = child 1 of node a (the cell tree's root); u < k[6] is
+ *     resolved as above with j counted over k[1..5], a larger u descends
+ *     the tree from aux.
+ * Unused key slots hold 0.  A key of all ones stands for the end of the
+ * distribution.
  */
 typedef struct rtf_forest {
     int32_t D;          /* number of distributions */
@@ -233,7 +242,7 @@ rtf_status rtf_check(const rtf_forest *f, hipStream_t stream);
 
 /* Synchronise and copy the forest to host buffers (each may be NULL):
  * h_nodes receives the n_total 16-byte node records as stored, h_cells the
- * m_total 32-byte guide cell records as stored, h_W uint64[D] the
+ * m_total 64-byte guide cell records as stored, h_W uint64[D] the
  * distributions' total weights. */
 rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, void *h_cells,
                              uint64_t *h_W, hipStream_t stream);

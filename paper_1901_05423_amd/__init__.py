@@ -27,7 +27,7 @@ RTF_ERR_ZERO_TOTAL = 5
 RTF_ERR_VALUE = 6
 
 NODE_BYTES = 16
-CELL_BYTES = 32
+CELL_BYTES = 64
 
 
 class RtfError(RuntimeError):
@@ -159,31 +159,31 @@ class Forest:
         return self.ws[off:off + NODE_BYTES * n].view(torch.int64).view(n, 2)
 
     def cell_view(self):
-        """Device view of the guide cell records: int64 [m_total, 4] holding
-        k0, k1, k2 and the (ref, c1) int32 pair."""
+        """Device view of the guide cell records: int64 [m_total, 8] holding
+        the seven keys k[0..6] and the (ref, aux) int32 pair."""
         torch = _torch()
         off = self.desc.cells - self.ws.data_ptr()
         return self.ws[off:off + CELL_BYTES * self.m_total].view(torch.int64).view(
-            self.m_total, 4)
+            self.m_total, 8)
 
     def export(self, stream=None, with_cells=False):
         """Host copies: key uint64[n], child int32[n, 2], table int32[m] (the guide
         entries), W uint64[D]; with ``with_cells`` also the cell records as
-        (keys uint64[m, 3], c1 int32[m])."""
+        (keys uint64[m, 7], aux int32[m])."""
         import numpy as np
         n, m = self.n_total, self.m_total
         raw = np.zeros((n, 2), np.uint64)
-        cells = np.zeros((m, 4), np.uint64)
+        cells = np.zeros((m, 8), np.uint64)
         W = np.zeros(self.D, np.uint64)
         p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         _check(lib().rtf_forest_export(ctypes.byref(self.desc), p(raw), p(cells), p(W),
                                        _stream(stream)), "rtf_forest_export")
         key = np.ascontiguousarray(raw[:, 0])
         child = np.ascontiguousarray(raw[:, 1]).view(np.int32).reshape(n, 2)
-        refs = np.ascontiguousarray(cells[:, 3]).view(np.int32).reshape(m, 2)
+        refs = np.ascontiguousarray(cells[:, 7]).view(np.int32).reshape(m, 2)
         table = np.ascontiguousarray(refs[:, 0])
         if with_cells:
-            return key, child, table, W, (np.ascontiguousarray(cells[:, :3]),
+            return key, child, table, W, (np.ascontiguousarray(cells[:, :7]),
                                           np.ascontiguousarray(refs[:, 1]))
         return key, child, table, W
 

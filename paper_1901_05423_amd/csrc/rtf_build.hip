@@ -78,10 +78,15 @@ __device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i)
     return lo;
 }
 
-__device__ inline void load_items(const uint32_t *w, int64_t i0, int64_t n, bool vec,
-                                  uint32_t *r) {
+// Load the ITEMS weights starting at i0.  FULL: every one is in range and w
+// is 16-byte aligned, so the loads are unconditional vector loads.  Else each
+// load reads a clamped, in-range index and the value is masked; neither form
+// branches, so the compiler need not wait for a load at a branch join and
+// several loads stay in flight.
+template <bool FULL>
+__device__ inline void load_items(const uint32_t *w, int64_t i0, int64_t n, uint32_t *r) {
     static_assert(ITEMS == 2 || ITEMS % 4 == 0, "vector loads of 8 or 16 bytes");
-    if (vec && i0 + ITEMS <= n) {
+    if constexpr (FULL) {
         if constexpr (ITEMS == 2) {
             const uint2 v = *reinterpret_cast<const uint2 *>(w + i0);
             r[0] = v.x;
@@ -99,7 +104,11 @@ __device__ inline void load_items(const uint32_t *w, int64_t i0, int64_t n, bool
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < ITEMS; ++e) r[e] = (i0 + e < n) ? w[i0 + e] : 0u;
+        for (int e = 0; e < ITEMS; ++e) {
+            const int64_t i = i0 + e;
+            const uint32_t v = w[i < n ? (i >= 0 ? i : 0) : n - 1];
+            r[e] = (i >= 0 && i < n) ? v : 0u;
+        }
     }
 }
 
@@ -134,20 +143,49 @@ __device__ inline Leaf make_leaf(uint64_t C, const Dist &P) {
     return L;
 }
 
-__device__ inline void store_cell(Cell *cells, int64_t g, uint64_t k0, uint64_t k1, uint64_t k2,
-                                  int32_t ref, int32_t c1) {
-    uint4 a, b;
-    a.x = (uint32_t)k0;
-    a.y = (uint32_t)(k0 >> 32);
-    a.z = (uint32_t)k1;
-    a.w = (uint32_t)(k1 >> 32);
-    b.x = (uint32_t)k2;
-    b.y = (uint32_t)(k2 >> 32);
-    b.z = (uint32_t)ref;
-    b.w = (uint32_t)c1;
+// A 64-byte cell record with four 16-byte stores.
+__device__ inline void store_cell(Cell *cells, int64_t g, const uint64_t *k, int32_t ref,
+                                  int32_t aux) {
     uint4 *p = reinterpret_cast<uint4 *>(cells + g);
-    p[0] = a;
-    p[1] = b;
+    p[0] = make_uint4((uint32_t)k[0], (uint32_t)(k[0] >> 32), (uint32_t)k[1], (uint32_t)(k[1] >> 32));
+    p[1] = make_uint4((uint32_t)k[2], (uint32_t)(k[2] >> 32), (uint32_t)k[3], (uint32_t)(k[3] >> 32));
+    p[2] = make_uint4((uint32_t)k[4], (uint32_t)(k[4] >> 32), (uint32_t)k[5], (uint32_t)(k[5] >> 32));
+    p[3] = make_uint4((uint32_t)k[6], (uint32_t)(k[6] >> 32), (uint32_t)ref, (uint32_t)aux);
+}
+
+// The record of a cell covered by interval i alone, whose keys are lo and hi.
+__device__ inline void store_covered(Cell *cells, int64_t g, uint64_t lo, uint64_t hi, int32_t i) {
+    const uint64_t k[7] = {lo, hi, 0, 0, 0, 0, 0};
+    store_cell(cells, g, k, ~i, ~i);
+}
+
+// The record of the cell whose first node is a, given the key and cell of a
+// and of leaves a+1 .. a+CELL_BOUNDS (cell < 0: no mass, or outside [0, n)),
+// the key of leaf a-1 and the cell tree's root c1 (used when the cell holds
+// more than CELL_BOUNDS lower bounds).
+__device__ inline void root_record(Cell *cells, int64_t g, int32_t a, uint64_t kprev,
+                                   const uint64_t *key, const int32_t *cell, int32_t c1) {
+    uint64_t k[7];
+    k[0] = key[0] == 0 ? 0 : kprev;  // 0 at a distribution start
+    k[1] = key[0];
+    int cnt = 1;  // lower bounds of the cell among a .. a+t-1
+    bool open = true;
+#pragma unroll
+    for (int t = 1; t <= CELL_BOUNDS; ++t) {
+        uint64_t v = 0;
+        if (open && cell[t] == cell[0]) {
+            v = key[t];
+            ++cnt;
+        } else if (open) {
+            // leaf a+t starts the next cell: the upper end of the cell's last
+            // interval, or the distribution's end
+            const bool same_dist = cell[t] >= 0 && key[t] != 0;
+            v = same_dist ? key[t] : KEY_END;
+            open = false;
+        }
+        k[t + 1] = v;
+    }
+    store_cell(cells, g, k, a, open ? c1 : ~cnt);
 }
 
 // List the guide-table run [lo, hi), covered by interval i with keys k0 and
@@ -186,56 +224,101 @@ __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t 
 // k_tile_sums: the prefix-sum pass over the weights (Sec. 2.6 notes that the
 // prefix sum of an inversion method computes efficiently in parallel)
 // ---------------------------------------------------------------------------
+// Each block sums TS_TILES tiles whose loads are all issued before the first
+// reduction, so that enough bytes are in flight to stream at HBM rate.
+constexpr int TS_TILES = 4;
+
+__device__ inline uint64_t wave_sum(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+template <bool BATCHED, bool FULL>
+__device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *s_wave,
+                                      uint64_t *s_thr) {
+    constexpr int NW = BT / 64;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    uint32_t r[TS_TILES][ITEMS];
+#pragma unroll
+    for (int k = 0; k < TS_TILES; ++k)
+        load_items<FULL>(a.w, (t0 + k) * TILE + (int64_t)tid * ITEMS, a.n_total, r[k]);
+    uint64_t sum[TS_TILES];
+#pragma unroll
+    for (int k = 0; k < TS_TILES; ++k) {
+        sum[k] = 0;
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e) sum[k] += r[k][e];
+    }
+    if (!BATCHED) {
+        // one distribution: only the tile totals are needed
+#pragma unroll
+        for (int k = 0; k < TS_TILES; ++k) {
+            const uint64_t ws = wave_sum(sum[k]);
+            if (lane == 0) s_wave[k * NW + w] = ws;
+        }
+        __syncthreads();
+        if (tid < TS_TILES && t0 + tid < a.ntiles) {
+            uint64_t tot = 0;
+#pragma unroll
+            for (int i = 0; i < NW; ++i) tot += s_wave[tid * NW + i];
+            a.tile_sum[t0 + tid] = tot;
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < TS_TILES; ++k) {
+        const int64_t t = t0 + k;
+        if (t >= a.ntiles) break;  // uniform across the block
+        uint64_t total;
+        const uint64_t ex = block_excl_scan<NW>(sum[k], s_wave, total);
+        if (tid == 0) a.tile_sum[t] = total;
+        s_thr[tid] = ex;
+        __syncthreads();
+        // distributions that start inside this tile: record the in-tile prefix
+        const int64_t base = t * TILE, end = base + TILE;
+        int32_t dlo;
+        {
+            int32_t lo = 0, hi = a.D;  // first d with elem_off[d] >= base
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (a.src_elem_off[mid] < base) lo = mid + 1;
+                else hi = mid;
+            }
+            dlo = lo;
+        }
+        for (int32_t d = dlo + tid; d < a.D; d += BT) {
+            int64_t e = a.src_elem_off[d];
+            if (e >= end) break;
+            int64_t off = e - base;
+            int64_t tq = off / ITEMS;
+            uint64_t L = s_thr[tq];
+            for (int64_t q = base + tq * ITEMS; q < e; ++q) L += a.w[q];
+            a.dist_local[d] = L;
+        }
+        __syncthreads();  // s_thr and s_wave are reused by the next tile
+    }
+}
+
 template <bool BATCHED>
 __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
-    __shared__ uint64_t s_wave[BT / 64];
+    __shared__ uint64_t s_wave[TS_TILES * (BT / 64)];
     __shared__ uint64_t s_thr[BT];
-    const int64_t t = blockIdx.x;
-    if (t == 0) {
-        // this build's status word and the offsets every later kernel reads
-        if (threadIdx.x == 0) {
+    const int tid = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * TS_TILES;
+    if (blockIdx.x == 0) {
+        // this build's status word, run list and the offsets later kernels read
+        if (tid == 0) {
             *a.status = 0u;
             *a.run_count = 0;
         }
-        for (int64_t q = threadIdx.x; q <= a.D; q += BT) {
+        for (int64_t q = tid; q <= a.D; q += BT) {
             a.elem_off[q] = BATCHED ? a.src_elem_off[q] : (q ? a.n_total : 0);
             a.cell_off[q] = BATCHED ? a.src_cell_off[q] : (q ? a.m_total : 0);
         }
     }
-    const int64_t base = t * TILE;
-    const int64_t i0 = base + (int64_t)threadIdx.x * ITEMS;
-    uint32_t r[ITEMS];
-    load_items(a.w, i0, a.n_total, vec, r);
-    uint64_t sum = 0;
-#pragma unroll
-    for (int e = 0; e < ITEMS; ++e) sum += r[e];
-    uint64_t total;
-    uint64_t ex = block_excl_scan<BT / 64>(sum, s_wave, total);
-    if (threadIdx.x == 0) a.tile_sum[t] = total;
-    if (!BATCHED) return;
-    s_thr[threadIdx.x] = ex;
-    __syncthreads();
-    // distributions that start inside this tile: record the in-tile prefix
-    const int64_t end = base + TILE;
-    int32_t dlo;
-    {
-        int32_t lo = 0, hi = a.D;  // first d with elem_off[d] >= base
-        while (lo < hi) {
-            int32_t mid = (lo + hi) >> 1;
-            if (a.src_elem_off[mid] < base) lo = mid + 1;
-            else hi = mid;
-        }
-        dlo = lo;
-    }
-    for (int32_t d = dlo + threadIdx.x; d < a.D; d += BT) {
-        int64_t e = a.src_elem_off[d];
-        if (e >= end) break;
-        int64_t off = e - base;
-        int64_t tq = off / ITEMS;
-        uint64_t L = s_thr[tq];
-        for (int64_t q = base + tq * ITEMS; q < e; ++q) L += a.w[q];
-        a.dist_local[d] = L;
-    }
+    if (vec && (t0 + TS_TILES) * TILE <= a.n_total) tile_sums_body<BATCHED, true>(a, t0, s_wave, s_thr);
+    else tile_sums_body<BATCHED, false>(a, t0, s_wave, s_thr);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,7 +419,9 @@ constexpr int LEAF_N = TILE + 2 * HALO;
 constexpr int LVL_N = LEAF_N - 1;  // real boundaries; lvl[LVL_N] is padding
 static_assert(LEAF_N % 8 == 0, "levels are read 8 at a time");
 static_assert(2 * HALO == 64, "wave 0 loads both halos, one leaf per lane");
-static_assert(WIN % 4 == 0 && (LEAF_N * 12) % 16 == 0, "16-byte clears of slot and window");
+constexpr int WIN_PER_WAVE = WIN / (BT / 64);  // a wave's share of the window
+static_assert(WIN % (4 * (BT / 64)) == 0 && (LEAF_N * 12) % 16 == 0, "16-byte clears of slot and window");
+static_assert(2 * WIN_PER_WAVE >= 4 * 64 * ((LEAF_N / 4 + BT - 1) / BT), "phase 3 list fits the window share");
 constexpr int32_t SLOT_EMPTY = INT32_MIN;  // never a node or leaf reference
 
 // Owner codes of the guide cells staged in the window: which local leaf a
@@ -354,6 +439,7 @@ struct alignas(16) TileSmem {
     uint64_t lvl8[LEAF_N / 8];
     uint64_t wave[BT / 64];
     int64_t c_begin;
+    int32_t win_hi;  // highest window position phase 4 wrote
     int32_t ndefer;
     int32_t items[DEFER_CAP];
 };
@@ -363,14 +449,20 @@ __device__ inline void push_item(TileSmem &sm, int32_t item) {
     if (k < DEFER_CAP) sm.items[k] = item;
 }
 
+__device__ inline int byte_at(uint64_t w, int p) { return (int)((w >> (8 * p)) & 0xff); }
+
 __device__ inline int lvl_at(const TileSmem &sm, int bi) {
     return (int)((sm.lvl8[bi >> 3] >> (8 * (bi & 7))) & 0xff);
 }
 
-// bit 7 of every byte of w (eight levels, each < 128) that is >= t
+// bit 7 of every byte of w (eight levels, each < 128) that is >= t, for
+// 0 <= t <= 128: a byte plus 128 - t reaches 128 exactly when it is >= t and
+// never carries into the next byte, so each 32-bit half is done on its own
 __device__ inline uint64_t ge_mask(uint64_t w, int t) {
-    const uint64_t ones = 0x0101010101010101ull;
-    return (w + (uint64_t)(128 - t) * ones) & (0x80ull * ones);
+    const uint32_t rep = __builtin_amdgcn_perm(0u, (uint32_t)(128 - t), 0u);  // byte 0 x4
+    const uint32_t lo = ((uint32_t)w + rep) & 0x80808080u;
+    const uint32_t hi = ((uint32_t)(w >> 32) + rep) & 0x80808080u;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 constexpr int SCAN_WORDS = SCAN_CAP / 8;
@@ -410,26 +502,105 @@ __device__ inline void link(TileSmem &sm, int pn, int side, int32_t ref) {
 
 // stage the record of cell c (owner code w) in the window, or store it
 // directly when the cell lies past the window
-__device__ inline void put_cell(TileSmem &sm, Cell *cells, int64_t c, int32_t w, int32_t lb0) {
+// (returns the window position written, or -1)
+__device__ inline int put_cell(TileSmem &sm, Cell *cells, int64_t c, int32_t w, int32_t lb0) {
     const int64_t x = c - sm.c_begin;
     if (x >= 0 && x < WIN) {
         sm.win[x] = w;
-        return;
+        return (int)x;
     }
     const int li = w & 0xffff;
     const int32_t g = lb0 + li;
-    if ((w & ~0xffff) == WIN_HEAD) store_cell(cells, c, sm.key[li - 1], sm.key[li], 0, ~(g - 1), ~(g - 1));
-    else store_cell(cells, c, sm.key[li], KEY_END, 0, ~g, ~g);  // WIN_TAIL
+    if ((w & ~0xffff) == WIN_HEAD) store_covered(cells, c, sm.key[li - 1], sm.key[li], g - 1);
+    else store_covered(cells, c, sm.key[li], KEY_END, g);  // WIN_TAIL
+    return -1;
 }
 
 __device__ inline void root_cell_record(const TileSmem &sm, Cell *cells, int64_t c, int li,
                                         int32_t lb0) {
-    const uint64_t kj = sm.key[li];
-    const int32_t cj = sm.cell[li], nc = sm.cell[li + 1];
-    const uint64_t nk = sm.key[li + 1];
-    const bool next_same = nc >= 0 && !(nk == 0 && nc != cj);
-    store_cell(cells, c, kj == 0 ? 0 : sm.key[li - 1], kj, next_same ? nk : KEY_END, lb0 + li,
-               sm.slot[2 * (li - HALO) + 1]);
+    uint64_t key[CELL_BOUNDS + 1];
+    int32_t cell[CELL_BOUNDS + 1];
+#pragma unroll
+    for (int t = 0; t <= CELL_BOUNDS; ++t) {
+        key[t] = sm.key[li + t];
+        cell[t] = sm.cell[li + t];
+    }
+    // child 1 of a cell's first node: the cell tree's root (read only when
+    // the cell holds more than CELL_BOUNDS leaves, so it is an internal node)
+    root_record(cells, c, lb0 + li, sm.key[li - 1], key, cell, sm.slot[2 * (li - HALO) + 1]);
+}
+
+// Phase 1 of k_build_tile (thread t owns ITEMS consecutive leaves): prefix
+// sums, keys and cells into LDS, plus HALO leaves on either side of the tile.
+// Every global load of the phase (weights, halo weights, tile prefix,
+// distribution parameters) is issued before the block scan and none sits
+// under a branch, so a block waits for one round trip.  FULL: the tile lies
+// inside [0, n) and the weights are 16-byte aligned.
+template <bool BATCHED, bool FULL>
+__device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
+    const int tid = threadIdx.x;
+    const int64_t base = t * TILE;
+    const int64_t n = a.n_total;
+    // halo leaves: lanes 0..HALO-1 of wave 0 the HALO leaves left of the
+    // tile, lanes HALO..63 the HALO leaves right of it; every lane loads a
+    // clamped index so that the load needs no branch
+    const bool left = tid < HALO;
+    const int64_t hi_ = base - HALO + tid + (left ? 0 : TILE);
+    const bool hexists = tid < 64 && hi_ >= 0 && hi_ < n;
+    const uint32_t hraw = a.w[hi_ < 0 ? 0 : (hi_ < n ? hi_ : n - 1)];
+    __builtin_amdgcn_sched_barrier(0);  // issue the halo load first
+    const int64_t i0 = base + (int64_t)tid * ITEMS;
+    const int li0 = HALO + tid * ITEMS;
+    uint32_t wv[ITEMS];
+    load_items<FULL>(a.w, i0, n, wv);
+    const uint64_t tp = a.tile_prefix[t];
+    int32_t dcur = 0;
+    if (BATCHED) dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
+    Dist P = a.dists[dcur];
+    const uint64_t hw = hexists ? hraw : 0u;
+    Dist HP = P;
+    if (BATCHED && tid < 64) HP = a.dists[hexists ? find_segment(a.elem_off, a.D, hi_) : 0];
+
+    uint64_t sum = 0;
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e) sum += wv[e];
+    uint64_t tile_total;
+    uint64_t G = tp + block_excl_scan<BT / 64>(sum, sm.wave, tile_total);
+    int64_t dend = P.eo + P.n;
+    const int live = FULL ? ITEMS : (int)(n - i0 < ITEMS ? (n - i0 > 0 ? n - i0 : 0) : ITEMS);
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e) {
+        Leaf L;
+        L.key = 0;
+        L.cell = -2;
+        if (e < live) {
+            if (BATCHED) {
+                while (i0 + e >= dend) {
+                    ++dcur;
+                    P = a.dists[dcur];
+                    dend = P.eo + P.n;
+                }
+            }
+            L = make_leaf(G - P.G0, P);
+        }
+        sm.key[li0 + e] = L.key;
+        sm.cell[li0 + e] = L.cell;
+        G += wv[e];
+    }
+    if (tid < 64) {
+        const uint64_t suf = wave_incl_suffix(left ? hw : 0);
+        const uint64_t pre = wave_incl_scan(left ? 0 : hw);
+        Leaf L;
+        L.key = 0;
+        L.cell = -2;
+        if (hexists) {
+            const uint64_t Gi = left ? tp - suf : tp + tile_total + pre - hw;
+            L = make_leaf(Gi - HP.G0, HP);
+        }
+        const int slot = left ? tid : TILE + tid;
+        sm.key[slot] = L.key;
+        sm.cell[slot] = L.cell;
+    }
 }
 
 template <bool BATCHED>
@@ -443,74 +614,11 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     if (tid == 0) sm.ndefer = 0;
 
     // ---- phase 1: keys and cells of the tile's leaves -----------------------
-    // Every global load of the phase (weights, halo weights, tile prefix,
-    // distribution parameters) is issued before the block scan, so a block
-    // waits for one round trip instead of three.
-    {
-        const int64_t i0 = base + (int64_t)tid * ITEMS;
-        const int li0 = HALO + tid * ITEMS;
-        uint32_t wv[ITEMS];
-        load_items(a.w, i0, n, vec, wv);
-        const uint64_t tp = a.tile_prefix[t];
-        int32_t dcur = 0;
-        if (BATCHED) dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
-        Dist P = a.dists[dcur];
-        // halo leaves: lanes 0..HALO-1 of wave 0 the HALO leaves left of the
-        // tile, lanes HALO..63 the HALO leaves right of it
-        const bool left = tid < HALO;
-        const int64_t hi_ = left ? base - HALO + tid : base + TILE + (tid - HALO);
-        const bool hexists = tid < 64 && hi_ >= 0 && hi_ < n;
-        uint64_t hw = 0;
-        Dist HP;
-        if (tid < 64) {
-            hw = hexists ? a.w[hi_] : 0u;
-            HP = a.dists[(BATCHED && hexists) ? find_segment(a.elem_off, a.D, hi_) : 0];
-        }
-
-        uint64_t sum = 0;
-#pragma unroll
-        for (int e = 0; e < ITEMS; ++e) sum += wv[e];
-        uint64_t tile_total;
-        uint64_t G = tp + block_excl_scan<BT / 64>(sum, sm.wave, tile_total);
-        int64_t dend = P.eo + P.n;
-        const int live = (int)(n - i0 < ITEMS ? (n - i0 > 0 ? n - i0 : 0) : ITEMS);
-#pragma unroll
-        for (int e = 0; e < ITEMS; ++e) {
-            Leaf L;
-            L.key = 0;
-            L.cell = -2;
-            if (e < live) {
-                if (BATCHED) {
-                    while (i0 + e >= dend) {
-                        ++dcur;
-                        P = a.dists[dcur];
-                        dend = P.eo + P.n;
-                    }
-                }
-                L = make_leaf(G - P.G0, P);
-            }
-            sm.key[li0 + e] = L.key;
-            sm.cell[li0 + e] = L.cell;
-            G += wv[e];
-        }
-        if (tid < 64) {
-            const uint64_t suf = wave_incl_suffix(left ? hw : 0);
-            const uint64_t pre = wave_incl_scan(left ? 0 : hw);
-            Leaf L;
-            L.key = 0;
-            L.cell = -2;
-            if (hexists) {
-                const uint64_t Gi = left ? tp - suf : tp + tile_total + pre - hw;
-                L = make_leaf(Gi - HP.G0, HP);
-            }
-            const int slot = left ? tid : TILE + tid;
-            sm.key[slot] = L.key;
-            sm.cell[slot] = L.cell;
-        }
-    }
+    if (vec && base + TILE <= n) build_keys<BATCHED, true>(a, sm, t);
+    else build_keys<BATCHED, false>(a, sm, t);
     __syncthreads();
 
-    // ---- phase 2: levels of all boundaries held; empty slots and window ----
+    // ---- phase 2: levels of all boundaries held; empty child slots ---------
     {
         // one level per thread and byte (consecutive lanes, no bank conflicts);
         // byte bi of the array is byte bi & 7 of word bi >> 3
@@ -524,9 +632,7 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     }
     {
         const int4 se = make_int4(SLOT_EMPTY, SLOT_EMPTY, SLOT_EMPTY, SLOT_EMPTY);
-        const int4 we = make_int4(WIN_EMPTY, WIN_EMPTY, WIN_EMPTY, WIN_EMPTY);
         for (int x = tid; x < 2 * TILE / 4; x += BT) reinterpret_cast<int4 *>(sm.slot)[x] = se;
-        for (int x = tid; x < WIN / 4; x += BT) reinterpret_cast<int4 *>(sm.win)[x] = we;
     }
     if (tid == 0) {
         // first guide cell whose record comes from a leaf of this tile
@@ -540,33 +646,91 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
             cb = P.co + P.m;
         }
         sm.c_begin = cb;
+        sm.win_hi = -1;
     }
     __syncthreads();
 
-    // ---- phase 3: parent links ---------------------------------------------
-    // internal nodes: boundaries of the window below SENT
-    for (int bi = tid; bi < LVL_N; bi += BT) {
-        const int l = lvl_at(sm, bi);
-        if (l >= SENT) continue;
-        const int L = nearest_ge_left(sm, bi - 1, l + 1);
-        const int R = nearest_ge_right(sm, bi + 1, l);
-        if (L < 0 || R < 0) continue;  // the parent is found by the fix-up
-        const int32_t ref = lb0 + bi + 1;
-        if (lvl_at(sm, L) > lvl_at(sm, R)) link(sm, R + 1, 0, ref);
-        else link(sm, L + 1, 1, ref);
-    }
-    // leaves that may hang from the tile's nodes
-    for (int li = HALO - 1 + tid; li < HALO + TILE; li += BT) {
-        if (sm.cell[li] < 0) continue;
-        const int ll = lvl_at(sm, li - 1), lr = lvl_at(sm, li);
-        const int32_t ref = ~(lb0 + li);
-        if (ll > lr) link(sm, li + 1, 0, ref);
-        else link(sm, li, 1, ref);
+    // ---- phase 3: parent links of the internal nodes ------------------------
+    // Only a boundary inside a cell (level below SENT) is a node under
+    // another node, and the leaf children follow from three neighbouring
+    // levels (phase 4).  Each wave lists its boundaries below SENT, about a
+    // quarter of them at m = n, in its share of the guide-cell window, then
+    // takes one listed boundary per lane, so the searches run on full waves.
+    // The wave clears its share of the window afterwards for phase 4.
+    {
+        const int wv = tid >> 6, lane = tid & 63;
+        uint16_t *list = reinterpret_cast<uint16_t *>(sm.win + wv * WIN_PER_WAVE);
+        int total = 0;  // uniform across the wave
+        for (int g0 = wv * 64; g0 < LEAF_N / 4; g0 += BT) {
+            const int g = g0 + lane;  // four boundaries 4g..4g+3
+            uint32_t fl = 0;
+            if (g < LEAF_N / 4) {
+                const uint32_t w4 = reinterpret_cast<const uint32_t *>(sm.lvl8)[g];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * g + q < LVL_N && ((w4 >> (8 * q)) & 0xff) < SENT) fl |= 1u << q;
+            }
+            const int c = __popc(fl);
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+            int pos = total + incl - c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (fl & (1u << q)) list[pos++] = (uint16_t)(4 * g + q);
+            total += __shfl(incl, 63, 64);
+        }
+        for (int k = lane; k < total; k += 64) {
+            const int bi = list[k];
+            const int wi = bi >> 3, p = bi & 7;
+            const bool has_l = wi > 0, has_r = wi + 1 < LEAF_N / 8;
+            const uint64_t wl = has_l ? sm.lvl8[wi - 1] : 0, wc = sm.lvl8[wi];
+            const uint64_t wr = has_r ? sm.lvl8[wi + 1] : 0;
+            const int l = byte_at(wc, p);
+            // L: nearest boundary left of bi with a level above l
+            int L, lL;
+            uint64_t mk = ge_mask(wc, l + 1) & ((1ull << (8 * p)) - 1);
+            if (mk) {
+                L = 8 * wi + (63 - clz64(mk)) / 8;
+                lL = byte_at(wc, L & 7);
+            } else if (has_l && (mk = ge_mask(wl, l + 1))) {
+                L = 8 * (wi - 1) + (63 - clz64(mk)) / 8;
+                lL = byte_at(wl, L & 7);
+            } else {
+                L = has_l ? nearest_ge_left(sm, 8 * (wi - 1) - 1, l + 1) : -1;
+                lL = L >= 0 ? lvl_at(sm, L) : 0;
+            }
+            // R: nearest boundary right of bi with a level at least l
+            int R, lR;
+            mk = p < 7 ? ge_mask(wc, l) & (~0ull << (8 * p + 8)) : 0;
+            if (mk) {
+                R = 8 * wi + __builtin_ctzll(mk) / 8;
+                lR = byte_at(wc, R & 7);
+            } else if (has_r && (mk = ge_mask(wr, l))) {
+                R = 8 * (wi + 1) + __builtin_ctzll(mk) / 8;
+                lR = byte_at(wr, R & 7);
+            } else {
+                R = has_r ? nearest_ge_right(sm, 8 * (wi + 2), l) : -1;
+                lR = R >= 0 ? lvl_at(sm, R) : 0;
+            }
+            if (R >= LVL_N) R = -1;       // the padding byte: beyond the window
+            if (L < 0 || R < 0) continue;  // the parent is found by the fix-up
+            const int32_t ref = lb0 + bi + 1;
+            if (lL > lR) link(sm, R + 1, 0, ref);
+            else link(sm, L + 1, 1, ref);
+        }
+        const int4 we = make_int4(WIN_EMPTY, WIN_EMPTY, WIN_EMPTY, WIN_EMPTY);
+        for (int x = lane; x < WIN_PER_WAVE / 4; x += 64)
+            reinterpret_cast<int4 *>(sm.win + wv * WIN_PER_WAVE)[x] = we;
     }
     __syncthreads();
 
     // ---- phase 4: node records; guide cells into the window ----------------
     const int live_nodes = (int)(n - base < TILE ? n - base : TILE);
+    int xmax = -1;  // highest window position this thread wrote
     for (int jl = tid; jl < live_nodes; jl += BT) {
         const int li = HALO + jl;
         const int32_t gj = lb0 + li;  // global node / leaf index
@@ -574,22 +738,31 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
         const int32_t cj = sm.cell[li];
         int32_t c0 = ~gj, c1 = ~gj;
         if (cj >= 0) {
-            const bool root = lvl_at(sm, li - 1) == SENT;
-            c0 = root ? ((kj == 0) ? ~gj : ~(gj - 1)) : sm.slot[2 * jl];
-            c1 = sm.slot[2 * jl + 1];
+            // boundary li - 1 is node gj's own; a leaf child follows from the
+            // levels of its two boundaries, an internal child was linked into
+            // the slot in phase 3
+            const int l2 = lvl_at(sm, li - 2), l1 = lvl_at(sm, li - 1), l0 = lvl_at(sm, li);
+            const bool root = l1 == SENT;
+            c0 = root ? ((kj == 0) ? ~gj : ~(gj - 1)) : (l2 > l1 ? ~(gj - 1) : sm.slot[2 * jl]);
+            c1 = l1 <= l0 ? ~gj : sm.slot[2 * jl + 1];
             if (c0 == SLOT_EMPTY || c1 == SLOT_EMPTY) push_item(sm, gj);
             // leaf gj+1 carries mass and belongs to gj's distribution
             const int32_t nc = sm.cell[li + 1];
             const bool next_same = nc >= 0 && !(sm.key[li + 1] == 0 && nc != cj);
             if (root) {
                 const int64_t x = cj - sm.c_begin;
-                if (x >= 0 && x < WIN) sm.win[x] = WIN_ROOT | li;
-                else root_cell_record(sm, a.cells, cj, li, lb0);
+                if (x >= 0 && x < WIN) {
+                    sm.win[x] = WIN_ROOT | li;
+                    xmax = max(xmax, (int)x);
+                } else {
+                    root_cell_record(sm, a.cells, cj, li, lb0);
+                }
                 const int32_t pc = sm.cell[li - 1];
                 if (kj != 0 && cj - pc > 1) {
                     if (cj - pc - 1 > RUN_CAP) push_run(a, pc + 1, cj, gj - 1, sm.key[li - 1], kj);
                     else
-                        for (int64_t c = pc + 1; c < cj; ++c) put_cell(sm, a.cells, c, WIN_HEAD | li, lb0);
+                        for (int64_t c = pc + 1; c < cj; ++c)
+                            xmax = max(xmax, put_cell(sm, a.cells, c, WIN_HEAD | li, lb0));
                 }
             }
             // the distribution's last leaf with mass covers the remaining cells
@@ -599,17 +772,22 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
                 if (cend - cj > 1) {
                     if (cend - cj - 1 > RUN_CAP) push_run(a, cj + 1, cend, gj, kj, KEY_END);
                     else
-                        for (int64_t c = cj + 1; c < cend; ++c) put_cell(sm, a.cells, c, WIN_TAIL | li, lb0);
+                        for (int64_t c = cj + 1; c < cend; ++c)
+                            xmax = max(xmax, put_cell(sm, a.cells, c, WIN_TAIL | li, lb0));
                 }
             }
         }
         // a deferred node's children are rewritten by the fix-up kernel
         store_node(a.nodes, gj, kj, c0, c1);
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) xmax = max(xmax, __shfl_xor(xmax, o, 64));
+    if ((tid & 63) == 0) atomicMax(&sm.win_hi, xmax);
     __syncthreads();
 
     // ---- phase 5: the staged guide cells, 64 consecutive records per wave ---
-    for (int x = tid; x < WIN; x += BT) {
+    const int span = sm.win_hi + 1;
+    for (int x = tid; x < span; x += BT) {
         const int32_t w = sm.win[x];
         if (w == WIN_EMPTY) continue;
         const int64_t c = sm.c_begin + x;
@@ -617,8 +795,8 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
         const int32_t g = lb0 + li;
         const int32_t kind = w & ~0xffff;
         if (kind == WIN_ROOT) root_cell_record(sm, a.cells, c, li, lb0);
-        else if (kind == WIN_HEAD) store_cell(a.cells, c, sm.key[li - 1], sm.key[li], 0, ~(g - 1), ~(g - 1));
-        else store_cell(a.cells, c, sm.key[li], KEY_END, 0, ~g, ~g);
+        else if (kind == WIN_HEAD) store_covered(a.cells, c, sm.key[li - 1], sm.key[li], g - 1);
+        else store_covered(a.cells, c, sm.key[li], KEY_END, g);
     }
     const int32_t nd = sm.ndefer;
     if (tid == 0) a.defer_count[t] = nd;
@@ -710,10 +888,6 @@ struct GlobalView {
         }
         return (int32_t)(g + 1);
     }
-    // leaf j+1 carries mass and belongs to the distribution of leaf j
-    __device__ bool next_same(const Leaf &Lj, const Leaf &Ln) const {
-        return Ln.cell >= 0 && !(Ln.key == 0 && Ln.cell != Lj.cell);
-    }
     // the record of node j, and whether j is the first node of its cell
     __device__ bool node(int64_t j, uint64_t &kj, int32_t &c0, int32_t &c1) const {
         Leaf Lj = leaf(j);
@@ -737,30 +911,48 @@ struct GlobalView {
     }
     // the guide cell record of the cell whose first node is j
     __device__ void root_cell(int64_t j, int32_t c1) const {
-        Leaf Lj = leaf(j), Ln = leaf(j + 1);
-        const uint64_t k0 = (Lj.key == 0) ? 0 : a.nodes[j - 1].key;
-        store_cell(a.cells, Lj.cell, k0, Lj.key, next_same(Lj, Ln) ? Ln.key : KEY_END,
-                   (int32_t)j, c1);
+        uint64_t key[CELL_BOUNDS + 1];
+        int32_t cell[CELL_BOUNDS + 1];
+#pragma unroll
+        for (int t = 0; t <= CELL_BOUNDS; ++t) {
+            const Leaf L = leaf(j + t);
+            key[t] = L.key;
+            cell[t] = L.cell;
+        }
+        const uint64_t kprev = key[0] == 0 ? 0 : a.nodes[j - 1].key;
+        root_record(a.cells, cell[0], (int32_t)j, kprev, key, cell, c1);
     }
 };
 
 template <bool BATCHED>
 __device__ void fixup_tile(const BuildArgs &a, int64_t t);
 
-// Grid-stride over tiles: most tiles defer nothing, so a few hundred blocks
-// that skip them quickly cost less than one block per tile.  Then all blocks
-// fill the listed guide-table run chunks, one chunk per block at a time.
+// Each block takes a contiguous range of tiles and reads their deferral
+// counts in parallel; most tiles defer nothing, so a few hundred blocks cost
+// less than one block per tile.  Then all blocks fill the listed guide-table
+// run chunks, one chunk per block at a time.
 template <bool BATCHED>
 __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
-    for (int64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-        if (a.defer_count[t] == 0) continue;  // uniform across the block
-        fixup_tile<BATCHED>(a, t);
+    __shared__ int32_t s_list[BT];
+    __shared__ int32_t s_n;
+    const int64_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
+    const int64_t t_lo = (int64_t)blockIdx.x * per;
+    const int64_t t_hi = t_lo + per < a.ntiles ? t_lo + per : a.ntiles;
+    for (int64_t t0 = t_lo; t0 < t_hi; t0 += BT) {
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
+        const int64_t t = t0 + threadIdx.x;
+        if (t < t_hi && a.defer_count[t] != 0) s_list[atomicAdd(&s_n, 1)] = (int32_t)threadIdx.x;
+        __syncthreads();
+        const int32_t nl = s_n;
+        for (int32_t q = 0; q < nl; ++q) fixup_tile<BATCHED>(a, t0 + s_list[q]);
+        __syncthreads();
     }
     const int64_t cap = run_chunk_cap(a.m_total);
     const int64_t nrun = *a.run_count < cap ? *a.run_count : cap;
     for (int64_t k = blockIdx.x; k < nrun; k += gridDim.x) {
         const RunChunk r = a.runs[k];
-        for (int64_t c = r.lo + threadIdx.x; c < r.hi; c += BT) store_cell(a.cells, c, r.k0, r.k1, 0, ~r.i, ~r.i);
+        for (int64_t c = r.lo + threadIdx.x; c < r.hi; c += BT) store_covered(a.cells, c, r.k0, r.k1, r.i);
     }
 }
 
@@ -787,14 +979,15 @@ __device__ void fixup_tile(const BuildArgs &a, int64_t t) {
 hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
     const bool vec = (reinterpret_cast<uintptr_t>(a.w) & 15) == 0;
     const dim3 grid((unsigned)a.ntiles);
+    const dim3 sumgrid((unsigned)((a.ntiles + TS_TILES - 1) / TS_TILES));
     const dim3 fixgrid((unsigned)(a.ntiles < 512 ? a.ntiles : 512));
     if (a.D > 1) {
-        hipLaunchKernelGGL(k_tile_sums<true>, grid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL(k_tile_sums<true>, sumgrid, dim3(BT), 0, st, a, vec);
         hipLaunchKernelGGL(k_dist_params<true>, dim3(1), dim3(PT), 0, st, a);
         hipLaunchKernelGGL(k_build_tile<true>, grid, dim3(BT), 0, st, a, vec);
         hipLaunchKernelGGL(k_fixup<true>, fixgrid, dim3(BT), 0, st, a);
     } else {
-        hipLaunchKernelGGL(k_tile_sums<false>, grid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL(k_tile_sums<false>, sumgrid, dim3(BT), 0, st, a, vec);
         hipLaunchKernelGGL(k_dist_params<false>, dim3(1), dim3(PT), 0, st, a);
         hipLaunchKernelGGL(k_build_tile<false>, grid, dim3(BT), 0, st, a, vec);
         hipLaunchKernelGGL(k_fixup<false>, fixgrid, dim3(BT), 0, st, a);

@@ -38,17 +38,27 @@ struct alignas(16) Node {
     int32_t c0, c1;
 };
 
-// Guide-table cell record.  `ref` is the paper's guide entry (Sec. 2.5, 3.2):
-// the cell's first node a, or ~i when one interval i covers the whole cell.
-// The keys needed to finish the common cases are stored beside it, so that a
-// sample whose cell holds at most one lower bound reads one 32-byte record:
-//   ref = a >= 0:  k0 = U_{a-1} (0 at a distribution start), k1 = U_a,
-//                  k2 = U_{a+1} or KEY_END, c1 = child 1 of node a;
-//   ref = ~i < 0:  k0 = U_i, k1 = U_{i+1} or KEY_END, k2 = 0, c1 = ref.
-// KEY_END stands for the upper end of the distribution (partial sum W).
-struct alignas(32) Cell {
-    uint64_t k0, k1, k2;
-    int32_t ref, c1;
+// Guide-table cell record, 64 bytes: one memory access per sample in the
+// common case.  `ref` is the paper's guide entry (Sec. 2.5, 3.2): the cell's
+// first node a, or ~i when one interval i covers the whole cell.  Beside it
+// the record keeps the keys that finish a sample without the tree:
+//   ref = ~i < 0:  k[0] = U_i, k[1] = U_{i+1} (KEY_END at the distribution's
+//                  end), aux = ref.
+//   ref = a >= 0:  the cell holds the c lower bounds U_a .. U_{a+c-1};
+//                  k[0] = U_{a-1} (0 at a distribution start) and
+//                  k[t] = U_{a+t-1} for t = 1 .. min(c + 1, 6), where
+//                  U_{a+c} (KEY_END at the distribution's end) is the upper
+//                  end of the cell's last interval.
+//                  c <= CELL_BOUNDS: aux = ~c, and the record resolves every
+//                  sample of the cell.
+//                  c > CELL_BOUNDS: aux = child 1 of node a, the root of the
+//                  cell's tree; the record resolves u < k[6], larger u
+//                  descend the tree from aux.
+// Key slots a record does not use hold 0.
+constexpr int CELL_BOUNDS = 5;
+struct alignas(64) Cell {
+    uint64_t k[7];
+    int32_t ref, aux;
 };
 constexpr uint64_t KEY_END = ~0ull;
 

@@ -29,14 +29,18 @@ __device__ inline Node load_node(const Node *nodes, int64_t j) {
 
 __device__ inline Cell load_cell(const Cell *cells, int64_t g) {
     const uint4 *p = reinterpret_cast<const uint4 *>(cells + g);
-    const uint4 a = p[0], b = p[1];
-    Cell c;
-    c.k0 = ((uint64_t)a.y << 32) | a.x;
-    c.k1 = ((uint64_t)a.w << 32) | a.z;
-    c.k2 = ((uint64_t)b.y << 32) | b.x;
-    c.ref = (int32_t)b.z;
-    c.c1 = (int32_t)b.w;
-    return c;
+    const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
+    Cell r;
+    r.k[0] = ((uint64_t)a.y << 32) | a.x;
+    r.k[1] = ((uint64_t)a.w << 32) | a.z;
+    r.k[2] = ((uint64_t)b.y << 32) | b.x;
+    r.k[3] = ((uint64_t)b.w << 32) | b.z;
+    r.k[4] = ((uint64_t)c.y << 32) | c.x;
+    r.k[5] = ((uint64_t)c.w << 32) | c.z;
+    r.k[6] = ((uint64_t)d.y << 32) | d.x;
+    r.ref = (int32_t)d.z;
+    r.aux = (int32_t)d.w;
+    return r;
 }
 
 // A sampled leaf with the keys of its interval's two ends (KEY_END for the
@@ -48,27 +52,36 @@ struct Hit {
 
 // Alg. 2: g = floor(xi * m); follow the reference until it names a leaf.
 // The cell record resolves the guide step and, for a cell that holds at most
-// one lower bound, the whole sample; otherwise the descent continues from the
-// cell's tree root.  A reference outside the forest, or a path longer than
-// the forest has nodes, can only come from a damaged workspace.
+// CELL_BOUNDS lower bounds (or for u below the record's last key), the whole
+// sample: the leaf is a - 1 plus the number of the cell's lower bounds at or
+// below u.  Otherwise the descent continues from the cell's tree root.  A
+// reference outside the forest, or a path longer than the forest has nodes,
+// can only come from a damaged workspace.
 __device__ inline Hit descend(const Node *nodes, const Cell *cells, const Dist &P, uint64_t u,
                               int64_t n_total) {
     const Cell c = load_cell(cells, P.co + (int64_t)mulhi64(u, (uint64_t)P.m));
     Hit h;
     if (c.ref < 0) {  // one interval covers the cell
         h.i = ~(int64_t)c.ref;
-        h.lo = c.k0;
-        h.hi = c.k1;
-    } else if (u < c.k1) {  // child 0 of the cell's first node: its left neighbour
-        h.i = (int64_t)c.ref - 1;
-        h.lo = c.k0;
-        h.hi = c.k1;
-    } else if (c.c1 < 0) {  // the cell's tree is a single leaf
-        h.i = ~(int64_t)c.c1;
-        h.lo = c.k1;
-        h.hi = c.k2;
+        h.lo = c.k[0];
+        h.hi = c.k[1];
+    } else if (c.aux < 0 || u < c.k[6]) {
+        const int lim = c.aux < 0 ? ~c.aux : CELL_BOUNDS;  // lower bounds held
+        int j = 0;
+        uint64_t lo = c.k[0], hi = c.k[1];
+#pragma unroll
+        for (int t = 1; t <= CELL_BOUNDS; ++t) {
+            if (t <= lim && c.k[t] <= u) {
+                j = t;
+                lo = c.k[t];
+                hi = c.k[t + 1];
+            }
+        }
+        h.i = (int64_t)c.ref - 1 + j;
+        h.lo = lo;
+        h.hi = hi;
     } else {
-        int32_t j = c.c1;
+        int32_t j = c.aux;
         for (int64_t steps = 0; j >= 0; ++steps) {
             if (j >= n_total || steps > n_total) {
                 h.i = -1;

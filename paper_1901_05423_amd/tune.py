@@ -41,13 +41,18 @@ def load_cache(path: str | None = None) -> dict:
         return {}
 
 
-def store_cache(entries: dict, path: str | None = None) -> None:
+def store_cache(entries: dict, path: str | None = None) -> bool:
+    """Write the cache; an unwritable location only loses the cache."""
     path = path or cache_path()
-    os.makedirs(os.path.dirname(path), exist_ok=True)
-    tmp = path + ".tmp"
-    with open(tmp, "w") as f:
-        json.dump(entries, f, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(entries, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+        return True
+    except OSError:
+        return False
 
 
 def forced_ratio():
@@ -74,17 +79,20 @@ def _time_ms(fn, reps=5):
     return e0.elapsed_time(e1) / reps
 
 
-def best_cell_ratio(w, u, candidates=CANDIDATES, use_cache=True, reps=5) -> float:
+def best_cell_ratio(w, u, candidates=CANDIDATES, use_cache=True, reps=5, with_times=False):
     """Cell ratio m/n with the fastest build + sample for uint32 weights `w`
-    (one distribution) and uniforms `u`, both device tensors."""
+    (one distribution) and uniforms `u`, both device tensors.  With
+    ``with_times`` also the measured ms per candidate ({} when the ratio came
+    from the environment or the cache)."""
     forced = forced_ratio()
     if forced is not None:
-        return forced
+        return (forced, {}) if with_times else forced
     from . import build, sample
     key = bucket_key(device_arch(), "single", w.numel(), u.numel())
     cache = load_cache() if use_cache else {}
     if key in cache:
-        return float(cache[key]["ratio"])
+        r = float(cache[key]["ratio"])
+        return (r, {}) if with_times else r
     n = w.numel()
     times = {}
     for r in candidates:
@@ -100,4 +108,4 @@ def best_cell_ratio(w, u, candidates=CANDIDATES, use_cache=True, reps=5) -> floa
     if use_cache:
         cache[key] = {"ratio": best, "ms": {str(k): v for k, v in times.items()}}
         store_cache(cache)
-    return best
+    return (best, {str(k): v for k, v in times.items()}) if with_times else best

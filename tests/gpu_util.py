@@ -64,23 +64,49 @@ def assert_samples(idx_gpu, x_gpu, idx_ref, x_ref):
         assert err.max() <= X_TOL, f"max |x - x_ref| = {err.max()}"
 
 
+CELL_BOUNDS = 5  # lower bounds a guide cell record holds
+
+
+def _cells_of(key, x, eo, co):
+    """Global guide cell of leaf x with key `key`: co_d + floor(key * m_d / 2^64)."""
+    d = np.searchsorted(eo, x, side="right") - 1
+    m = (co[d + 1] - co[d]).astype(np.uint64)
+    kh, kl = key >> np.uint64(32), key & np.uint64(0xFFFFFFFF)
+    hi = (kh * m + ((kl * m) >> np.uint64(32))) >> np.uint64(32)
+    return co[d] + hi.astype(np.int64)
+
+
 def expected_cells(ref):
-    """The repeated keys and child each guide cell record must hold, derived
-    from the oracle forest (see the cell record in include/rtforest.h)."""
+    """The keys and aux field each 64-byte guide cell record must hold, derived
+    from the oracle forest (the record is described in include/rtforest.h)."""
     MAX = np.uint64(TWO64 - 1)
-    key, child, table, eo = ref.key, ref.child, ref.table.astype(np.int64), ref.elem_off
+    key, child, table = ref.key, ref.child, ref.table.astype(np.int64)
+    eo, co = ref.elem_off.astype(np.int64), ref.cell_off.astype(np.int64)
+    n, m = key.size, table.size
     node = table >= 0
     a = np.where(node, table, ~table)  # first node a, or covering leaf i
-    end = eo[np.searchsorted(eo, a, side="right")]
-    nxt_ok = (a + 1 < end)
-    nxt = np.where(nxt_ok, key[np.minimum(a + 1, key.size - 1)], MAX)
-    nxt = np.where(nxt == MAX, MAX, nxt)
+    end = eo[np.searchsorted(eo, a, side="right")]  # end of a's distribution
+    g = np.arange(m, dtype=np.int64)
+    K = np.zeros((m, 7), np.uint64)
     prev = np.where(key[a] == 0, np.uint64(0), key[np.maximum(a - 1, 0)])
-    k0 = np.where(node, prev, key[a])
-    k1 = np.where(node, key[a], nxt)
-    k2 = np.where(node, nxt, np.uint64(0))
-    c1 = np.where(node, child[a, 1], table).astype(np.int32)
-    return np.stack([k0, k1, k2], axis=1).astype(np.uint64), c1
+    nxt = np.where(a + 1 < end, key[np.minimum(a + 1, n - 1)], MAX)
+    K[:, 0] = np.where(node, prev, key[a])
+    K[:, 1] = np.where(node, key[a], nxt)
+    opened = node.copy()
+    cnt = np.ones(m, np.int64)
+    for t in range(1, CELL_BOUNDS + 1):
+        x = a + t
+        xc = np.minimum(x, n - 1)
+        kx = key[xc]
+        live = (x < end) & (kx != MAX)
+        cx = np.where(live, _cells_of(np.where(live, kx, 0), xc, eo, co), -1)
+        incell = opened & live & (cx == g)
+        closing = opened & ~incell
+        K[:, t + 1] = np.where(incell, kx, np.where(closing, np.where(live, kx, MAX), np.uint64(0)))
+        cnt += incell
+        opened &= incell
+    aux = np.where(node, np.where(opened, child[a, 1], ~cnt), table).astype(np.int32)
+    return K, aux
 
 
 def assert_forest(f, ref, what=""):
