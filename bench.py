@@ -30,6 +30,44 @@ if ROOT not in sys.path:
 METRIC = ("samples/s + build Melem/s at n=2^24 (% HBM peak) vs binary search, bit-exact")
 HBM_PEAK_GBS = 8000.0
 NODE_B, CELL_B, U_B, IDX_B, X_B, W_B = 16, 64, 8, 4, 8, 4
+# Bytes the memory system moves for one random load: a whole 128-byte line.
+# Measured with the L2 request-size counters (TCC_EA0_RDREQ_{32B,64B,128B}):
+# every read request k_sample makes is a 128-byte request.
+LINE_B = 128
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def source_hash() -> str:
+    """Hash of the library's HIP sources and header; a committed counter
+    summary carries the hash it was taken with."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1901_05423_amd", "csrc", "*"))
+                   + glob.glob(os.path.join(ROOT, "include", "*.h")))
+    for fn in files:
+        h.update(os.path.basename(fn).encode())
+        with open(fn, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+    (calibrated FETCH_SIZE + WRITE_SIZE), or None when there is none or the
+    sources changed since the counters were taken."""
+    path = os.path.join(PROFILE_DIR, f"{kernel}_{workload}.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    if f"source_hash: {source_hash()}" not in text:
+        return None
+    for line in text.splitlines():
+        cols = [c.strip() for c in line.split("|")]
+        if len(cols) > 9 and cols[1].startswith(f"`rtf::{kernel}"):
+            return (float(cols[8]) + float(cols[9])) * 2 ** 20
+    return None
 
 
 def parse():
@@ -54,11 +92,12 @@ def parse():
 
 def sample_bytes_model(key, child, table, K, aux, m, u):
     """Replay Alg. 2 with the cell records on the host (exported forest,
-    subsample of the uniforms) and return the mean algorithmic bytes a sample
-    reads beyond its streams: the 64-byte cell record, plus 16 bytes per node
-    record of the descent and 32 bytes for the two keys of the position when
-    the record does not resolve the sample; also the mean descent length and
-    the fraction of samples the record resolves."""
+    subsample of the uniforms) and return the mean useful bytes a sample reads
+    beyond its streams (the 64-byte cell record, plus 16 bytes per node record
+    of the descent and 32 bytes for the two keys of the position when the
+    record does not resolve the sample), the mean number of dependent random
+    loads per sample (the record, each node, the key pair), the mean descent
+    length and the fraction of samples the record resolves."""
     g = ((u.astype(object) * m) >> 64).astype(np.int64)
     ref = table[g].astype(np.int64)
     ax = aux[g].astype(np.int64)
@@ -73,8 +112,9 @@ def sample_bytes_model(key, child, table, K, aux, m, u):
         j[active] = np.where(go_left, child[ja, 0], child[ja, 1])
         active = j >= 0
     extra = CELL_B + deeper * (NODE_B * visits + 2 * NODE_B)
-    return float(extra.mean()), float(visits[deeper].mean()) if deeper.any() else 0.0, \
-        float(1.0 - deeper.mean())
+    loads = 1 + deeper * (visits + 1)
+    return float(extra.mean()), float(loads.mean()), \
+        float(visits[deeper].mean()) if deeper.any() else 0.0, float(1.0 - deeper.mean())
 
 
 def timed(fn, start, stop, reps):
@@ -178,8 +218,10 @@ def main():
     # position reads (one record pair)
     key, child, table, W, (K, aux) = f.export(with_cells=True)
     sub = u_h[:: max(1, S // (1 << 20))]
-    extra, dbar, resolved = sample_bytes_model(key, child, table, K, aux, m, sub)
-    per_sample = U_B + IDX_B + X_B + extra
+    extra, loads, dbar, resolved = sample_bytes_model(key, child, table, K, aux, m, sub)
+    streams = U_B + IDX_B + X_B
+    per_sample = streams + LINE_B * loads  # what the memory system moves
+    useful = streams + extra               # the bytes the search uses
     sample_bytes = per_sample * S
     build_bytes = (W_B + NODE_B) * n + CELL_B * m
     achieved = sample_bytes / (t_sample * 1e-3) / 1e9
@@ -216,8 +258,13 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": counted_traffic("k_sample", f"h24_{args.kind}")
+            if m == n // 4 and S == 1 << 26 and n == 1 << 24 else None,
             "bytes_per_sample": per_sample,
+            "random_loads_per_sample": loads,
+            "line_bytes": LINE_B,
+            "useful_bytes_per_sample": useful,
+            "useful_frac": useful * S / (t_sample * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "wall_s_timed": wall,
     }
