@@ -8,8 +8,10 @@
 // and with a_s = g_s / (n_d w_{i_s}):
 //   dL/dv_k = A_d - sum_{j > k} B_j - D_k,
 //   A_d = sum_s a_s xi_s,  B_j = sum_{i_s = j} a_s,  D_j = sum_{i_s = j} a_s frac_s.
-// k_bscatter accumulates A, B, D with FP64 atomics; k_bcombine does the
-// segmented suffix sum of B per distribution.
+// k_bscatter accumulates A, B, D; k_bcombine does the segmented suffix sum of
+// B per distribution.  A block whose samples all belong to one distribution
+// of at most LBINS elements sums B and D in LDS first and adds each bin to
+// global memory once; otherwise every sample adds with FP64 global atomics.
 #include "rtf_internal.h"
 
 namespace rtf {
@@ -17,7 +19,8 @@ namespace rtf {
 namespace {
 
 constexpr int BB = 256;
-constexpr int CHUNK = BB * 32;  // samples per scatter block
+constexpr int CHUNK = BB * 256;  // samples per scatter block
+constexpr int LBINS = 4096;      // bins a block can sum in LDS (2 x 32 KB)
 
 __device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
     int32_t lo = 0, hi = D;
@@ -61,11 +64,18 @@ __global__ __launch_bounds__(BB) void k_bscatter(const Node *__restrict__ nodes,
                                                  const double *__restrict__ scale, double *B,
                                                  double *Dv, double *A) {
     __shared__ double s_red[BB / 64];
+    __shared__ double s_b[LBINS], s_d[LBINS];
     const int64_t c0 = (int64_t)blockIdx.x * CHUNK;
     const int64_t c1 = c0 + CHUNK < S ? c0 + CHUNK : S;
     const int32_t d_first = BATCHED ? find_segment(soff, D, c0) : 0;
     const int32_t d_last = BATCHED ? find_segment(soff, D, c1 - 1) : 0;
     const bool uniform = d_first == d_last;
+    const int64_t n_first = dists[d_first].n;
+    const bool priv = uniform && n_first <= LBINS;  // uniform across the block
+    if (priv) {
+        for (int64_t k = threadIdx.x; k < n_first; k += BB) s_b[k] = s_d[k] = 0.0;
+        __syncthreads();
+    }
     int32_t d = d_first;
     int64_t dend = BATCHED ? soff[d + 1] : S;
     double acc = 0.0;
@@ -93,8 +103,21 @@ __global__ __launch_bounds__(BB) void k_bscatter(const Node *__restrict__ nodes,
         const double xi = ldexp((double)us, -64);
         const double a = gx[s] / ((double)P.n * (wi / scale[d]));
         acc += a * xi;
-        unsafeAtomicAdd(B + i, a);
-        unsafeAtomicAdd(Dv + i, a * frac);
+        if (priv) {
+            atomicAdd(s_b + li, a);
+            atomicAdd(s_d + li, a * frac);
+        } else {
+            unsafeAtomicAdd(B + i, a);
+            unsafeAtomicAdd(Dv + i, a * frac);
+        }
+    }
+    if (priv) {
+        __syncthreads();
+        const int64_t eo = dists[d_first].eo;
+        for (int64_t k = threadIdx.x; k < n_first; k += BB) {
+            if (s_b[k] != 0.0) unsafeAtomicAdd(B + eo + k, s_b[k]);
+            if (s_d[k] != 0.0) unsafeAtomicAdd(Dv + eo + k, s_d[k]);
+        }
     }
     if (uniform) {
         const double t = block_sum(acc, s_red);

@@ -690,31 +690,40 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
             const uint64_t wl = has_l ? sm.lvl8[wi - 1] : 0, wc = sm.lvl8[wi];
             const uint64_t wr = has_r ? sm.lvl8[wi + 1] : 0;
             const int l = byte_at(wc, p);
-            // L: nearest boundary left of bi with a level above l
+            // L: nearest boundary left of bi with a level above l, in wc below
+            // byte p or else in wl (chosen by selects, one bit search); only
+            // a subtree wider than the two words scans on in LDS
             int L, lL;
-            uint64_t mk = ge_mask(wc, l + 1) & ((1ull << (8 * p)) - 1);
-            if (mk) {
-                L = 8 * wi + (63 - clz64(mk)) / 8;
-                lL = byte_at(wc, L & 7);
-            } else if (has_l && (mk = ge_mask(wl, l + 1))) {
-                L = 8 * (wi - 1) + (63 - clz64(mk)) / 8;
-                lL = byte_at(wl, L & 7);
-            } else {
-                L = has_l ? nearest_ge_left(sm, 8 * (wi - 1) - 1, l + 1) : -1;
-                lL = L >= 0 ? lvl_at(sm, L) : 0;
+            {
+                const uint64_t mc = ge_mask(wc, l + 1) & ((1ull << (8 * p)) - 1);
+                const uint64_t mw = has_l ? ge_mask(wl, l + 1) : 0;
+                const bool in_c = mc != 0;
+                const uint64_t mk = in_c ? mc : mw;
+                const uint64_t wsel = in_c ? wc : wl;
+                const int pos = (63 - clz64(mk | 0x80)) >> 3;  // byte 0 if mk == 0
+                L = 8 * (in_c ? wi : wi - 1) + pos;
+                lL = byte_at(wsel, pos);
+                if (mk == 0) {
+                    L = has_l ? nearest_ge_left(sm, 8 * (wi - 1) - 1, l + 1) : -1;
+                    lL = L >= 0 ? lvl_at(sm, L) : 0;
+                }
             }
-            // R: nearest boundary right of bi with a level at least l
+            // R: nearest boundary right of bi with a level at least l, in wc
+            // above byte p or else in wr
             int R, lR;
-            mk = p < 7 ? ge_mask(wc, l) & (~0ull << (8 * p + 8)) : 0;
-            if (mk) {
-                R = 8 * wi + __builtin_ctzll(mk) / 8;
-                lR = byte_at(wc, R & 7);
-            } else if (has_r && (mk = ge_mask(wr, l))) {
-                R = 8 * (wi + 1) + __builtin_ctzll(mk) / 8;
-                lR = byte_at(wr, R & 7);
-            } else {
-                R = has_r ? nearest_ge_right(sm, 8 * (wi + 2), l) : -1;
-                lR = R >= 0 ? lvl_at(sm, R) : 0;
+            {
+                const uint64_t mc = p < 7 ? ge_mask(wc, l) & (~0ull << (8 * p + 8)) : 0;
+                const uint64_t mw = has_r ? ge_mask(wr, l) : 0;
+                const bool in_c = mc != 0;
+                const uint64_t mk = in_c ? mc : mw;
+                const uint64_t wsel = in_c ? wc : wr;
+                const int pos = __builtin_ctzll(mk | (1ull << 63)) >> 3;
+                R = 8 * (in_c ? wi : wi + 1) + pos;
+                lR = byte_at(wsel, pos);
+                if (mk == 0) {
+                    R = has_r ? nearest_ge_right(sm, 8 * (wi + 2), l) : -1;
+                    lR = R >= 0 ? lvl_at(sm, R) : 0;
+                }
             }
             if (R >= LVL_N) R = -1;       // the padding byte: beyond the window
             if (L < 0 || R < 0) continue;  // the parent is found by the fix-up
