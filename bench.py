@@ -328,6 +328,12 @@ def common(metric, unit, value, ms, args, dtype, workload, **extra):
     return out
 
 
+def batch_ratio(args):
+    """Guide cells per weight for the batched workloads: --cell-ratio, else
+    the ratio the autotuner picks for one distribution at n = 2^24 (1/4)."""
+    return args.cell_ratio if args.cell_ratio is not None else 0.25
+
+
 def run_c4(args):
     """10,000 uneven distributions: quantise + build + sample in one launch
     sequence, eagerly and as one replayed graph, against one library call
@@ -343,7 +349,10 @@ def run_c4(args):
     v, u = torch.from_numpy(v_h).to(dev), torch.from_numpy(u_h).to(dev)
     eo, so = torch.from_numpy(eo_h).to(dev), torch.from_numpy(so_h).to(dev)
     n, S, D = int(eo_h[-1]), int(so_h[-1]), eo_h.size - 1
-    plan = BatchedPlan(eo, eo, so, n, n, S)
+    ratio = batch_ratio(args)
+    co = rtf.cells_like(eo, ratio)
+    mt = int(co[-1].item())
+    plan = BatchedPlan(eo, co, so, n, mt, S)
     for _ in range(args.warmup):
         plan.run(v, u)
     plan.check()
@@ -358,7 +367,7 @@ def run_c4(args):
     for d in range(D):
         a, b = int(eo_h[d]), int(eo_h[d + 1])
         q, _ = rtf.quantize(v[a:b])
-        f = rtf.build(q, b - a)
+        f = rtf.build(q, max(1, int(round(ratio * (b - a)))))
         rtf.sample(f, u[int(so_h[d]):int(so_h[d + 1])])
         forests.append(f)
         if len(forests) > 64:
@@ -367,7 +376,7 @@ def run_c4(args):
     t_b3 = (time.perf_counter() - t0) * 1e3
     res = common(METRIC, "samples/s", S / (t_graph * 1e-3), t_graph, args, "u64",
                  f"C4: {D} distributions, sizes log-uniform in [16, 65536] (n_total={n}), "
-                 f"uniform or Pareto(1.2) weights, m_d=n_d, {S} uniforms (64 per 1k weights), "
+                 f"uniform or Pareto(1.2) weights, m_d={ratio:g}n_d, {S} uniforms (64 per 1k weights), "
                  "quantise + build + sample with x",
                  elements_per_s=n / (t_graph * 1e-3), ms_eager=t_eager, ms_graph=t_graph,
                  ms_per_distribution_launches=t_b3,
@@ -392,9 +401,12 @@ def run_c3(args):
     v, u2 = torch.from_numpy(v_h).to(dev), torch.from_numpy(u_h).to(dev)
     eo = torch.from_numpy(eo_h).to(dev)
     n = int(eo_h[-1])
+    ratio = batch_ratio(args)
+    co = rtf.cells_like(eo, ratio)
+    mt = int(co[-1].item())
     q = torch.empty(n, dtype=torch.uint32, device=dev)
     scale = torch.empty(R + 1, dtype=torch.float64, device=dev)
-    ws = torch.empty(rtf.lib().rtf_workspace_bytes_batched(R + 1, n, n), dtype=torch.uint8,
+    ws = torch.empty(rtf.lib().rtf_workspace_bytes_batched(R + 1, n, mt), dtype=torch.uint8,
                      device=dev)
     rc = torch.empty(2 * pairs, dtype=torch.int32, device=dev)
     xy = torch.empty(2 * pairs, dtype=torch.float64, device=dev)
@@ -402,12 +414,12 @@ def run_c3(args):
 
     def build():
         rtf.quantize(v, eo, out=(q, scale))
-        st["f"] = rtf.build_batched(q, eo, eo) if "f" not in st else _rebuild(st["f"])
+        st["f"] = rtf.build_batched(q, eo, co) if "f" not in st else _rebuild(st["f"])
 
     def _rebuild(f):
         import ctypes
-        rtf._check(rtf.lib().rtf_build_batched(rtf._ptr(q), rtf._ptr(eo), rtf._ptr(eo), R + 1, n,
-                                               n, rtf._ptr(f.ws), f.ws.numel(), rtf._stream(),
+        rtf._check(rtf.lib().rtf_build_batched(rtf._ptr(q), rtf._ptr(eo), rtf._ptr(co), R + 1, n,
+                                               mt, rtf._ptr(f.ws), f.ws.numel(), rtf._stream(),
                                                ctypes.byref(f.desc)), "rtf_build_batched")
         return f
 
@@ -419,7 +431,7 @@ def run_c3(args):
     ms = t_build + t_sample
     res = common(METRIC, "pairs/s", pairs / (ms * 1e-3), ms, args, "u64",
                  "C3: 4096x4096 log-normal(0,1.5) map + 8 hot spots (1e4, sigma 3 px); marginal + "
-                 "4096 rows quantised and built as one batch (m_d=n_d); 2^27 (row, col) pairs + "
+                 f"4096 rows quantised and built as one batch (m_d={ratio:g}n_d); 2^27 (row, col) pairs + "
                  "sub-pixel positions",
                  ms_build=t_build, ms_sample=t_sample,
                  build_melem_s=n / (t_build * 1e-3) / 1e6,

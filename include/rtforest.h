@@ -179,6 +179,8 @@ rtf_status rtf_sample_batched(const rtf_forest *f, const int64_t *sample_off,
  *   out_rc   int32[2S]: (r, c) per pair
  *   out_xy   double[2S]: (y, x) continuous positions of the row and the
  *            column, or NULL
+ * u2 and out_xy must be 16-byte aligned and out_rc 8-byte aligned (pairs
+ * move as vectors); otherwise RTF_ERR_INVALID_ARG.
  */
 rtf_status rtf_sample_2d(const rtf_forest *f, const uint64_t *u2, int64_t S,
                          int32_t *out_rc, double *out_xy, hipStream_t stream);

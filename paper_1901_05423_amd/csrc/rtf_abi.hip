@@ -15,7 +15,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace layout of a forest of D distributions, n_total leaves, m_total cells.
 struct Layout {
-    size_t status, nodes, cells, dists, eoff, coff, tsum, tpre, dloc, dcnt, ditems, runs, total;
+    size_t status, nodes, cells, dists, eoff, coff, tsum, tpre, dloc, tdist, dcnt, ditems, runs,
+        total;
     int64_t ntiles;
 };
 
@@ -41,6 +42,8 @@ Layout make_layout(int32_t D, int64_t n, int64_t m) {
     o = align256(o + sizeof(uint64_t) * (size_t)L.ntiles);
     L.dloc = o;
     o = align256(o + sizeof(uint64_t) * (size_t)D);
+    L.tdist = o;
+    o = align256(o + sizeof(int32_t) * (size_t)(L.ntiles + 2));
     L.dcnt = o;
     o = align256(o + sizeof(int32_t) * (size_t)L.ntiles);
     L.ditems = o;
@@ -105,6 +108,7 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     a.tile_sum = reinterpret_cast<uint64_t *>(b + L.tsum);
     a.tile_prefix = reinterpret_cast<uint64_t *>(b + L.tpre);
     a.dist_local = reinterpret_cast<uint64_t *>(b + L.dloc);
+    a.tile_dist = reinterpret_cast<int32_t *>(b + L.tdist);
     a.defer_count = reinterpret_cast<int32_t *>(b + L.dcnt);
     a.defer_items = reinterpret_cast<int32_t *>(b + L.ditems);
     a.run_count = reinterpret_cast<int32_t *>(b + L.status + 64);  // in the status block
@@ -179,6 +183,9 @@ rtf_status rtf_sample_batched(const rtf_forest *f, const int64_t *sample_off, co
 rtf_status rtf_sample_2d(const rtf_forest *f, const uint64_t *u2, int64_t S, int32_t *out_rc,
                          double *out_xy, hipStream_t stream) {
     if (!forest_ok(f) || f->D < 2 || !sample_args_ok(u2, S, out_rc, out_xy))
+        return RTF_ERR_INVALID_ARG;
+    // pairs are moved as 16-byte (u2, out_xy) and 8-byte (out_rc) vectors
+    if (S > 0 && (!aligned(u2, 16) || !aligned(out_rc, 8) || (out_xy && !aligned(out_xy, 16))))
         return RTF_ERR_INVALID_ARG;
     if (S == 0) return RTF_OK;
     return from_hip(launch_sample_2d(static_cast<const Node *>(f->nodes),

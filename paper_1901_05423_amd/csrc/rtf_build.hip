@@ -67,12 +67,38 @@ __device__ inline uint64_t block_excl_scan(uint64_t x, uint64_t *s_wave, uint64_
     return off + inc - x;
 }
 
-// index d with off[d] <= i < off[d+1] over off[0..D]
-__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
-    int32_t lo = 0, hi = D;  // off[lo] <= i < off[hi]
+// index d in [lo, hi) with off[d] <= i < off[d+1], given off[lo] <= i < off[hi]
+__device__ inline int32_t find_segment_in(const int64_t *off, int32_t lo, int32_t hi, int64_t i) {
     while (hi - lo > 1) {
         int32_t mid = (lo + hi) >> 1;
         if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// index d with off[d] <= i < off[d+1] over off[0..D]
+__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
+    return find_segment_in(off, 0, D, i);
+}
+
+// first d in [0, D] with off[d] > i (off[0..D] non-decreasing)
+__device__ inline int32_t upper_bound(const int64_t *off, int32_t D, int64_t i) {
+    int32_t lo = 0, hi = D + 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// first d in [0, D] with off[d] >= i
+__device__ inline int32_t lower_bound(const int64_t *off, int32_t D, int64_t i) {
+    int32_t lo = 0, hi = D + 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (off[mid] < i) lo = mid + 1;
         else hi = mid;
     }
     return lo;
@@ -236,7 +262,7 @@ __device__ inline uint64_t wave_sum(uint64_t x) {
 
 template <bool BATCHED, bool FULL>
 __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *s_wave,
-                                      uint64_t *s_thr) {
+                                      uint64_t *s_thr, int32_t *s_first) {
     constexpr int NW = BT / 64;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     uint32_t r[TS_TILES][ITEMS];
@@ -266,27 +292,37 @@ __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *
         }
         return;
     }
+    // per tile, two searches over the caller's offsets, all in parallel: the
+    // first distribution starting at or after the tile's first element
+    // (lanes 0..TS_TILES-1), and the distribution holding that element
+    // (lanes TS_TILES..2 TS_TILES-1, into tile_dist); the block of the last
+    // tile also fills tile_dist[ntiles] and tile_dist[ntiles + 1]
+    if (tid < 2 * TS_TILES + 1) {
+        const int k = tid < 2 * TS_TILES ? tid % TS_TILES : 0;
+        const int64_t t = tid < 2 * TS_TILES ? t0 + k : a.ntiles;
+        const int64_t i = t * TILE < a.n_total ? t * TILE : a.n_total - 1;
+        if (tid < TS_TILES) {
+            if (t < a.ntiles) s_first[k] = lower_bound(a.src_elem_off, a.D, t * TILE);
+        } else if (tid < 2 * TS_TILES) {
+            if (t < a.ntiles) a.tile_dist[t] = upper_bound(a.src_elem_off, a.D, i) - 1;
+        } else if (t0 + TS_TILES >= a.ntiles) {
+            const int32_t d = upper_bound(a.src_elem_off, a.D, i) - 1;
+            a.tile_dist[a.ntiles] = d;
+            a.tile_dist[a.ntiles + 1] = d;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < TS_TILES; ++k) {
         const int64_t t = t0 + k;
         if (t >= a.ntiles) break;  // uniform across the block
         uint64_t total;
-        const uint64_t ex = block_excl_scan<NW>(sum[k], s_wave, total);
+        const uint64_t ex = block_excl_scan<NW>(sum[k], s_wave, total);  // has barriers
         if (tid == 0) a.tile_sum[t] = total;
         s_thr[tid] = ex;
         __syncthreads();
         // distributions that start inside this tile: record the in-tile prefix
         const int64_t base = t * TILE, end = base + TILE;
-        int32_t dlo;
-        {
-            int32_t lo = 0, hi = a.D;  // first d with elem_off[d] >= base
-            while (lo < hi) {
-                int32_t mid = (lo + hi) >> 1;
-                if (a.src_elem_off[mid] < base) lo = mid + 1;
-                else hi = mid;
-            }
-            dlo = lo;
-        }
+        const int32_t dlo = s_first[k];
         for (int32_t d = dlo + tid; d < a.D; d += BT) {
             int64_t e = a.src_elem_off[d];
             if (e >= end) break;
@@ -304,6 +340,7 @@ template <bool BATCHED>
 __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
     __shared__ uint64_t s_wave[TS_TILES * (BT / 64)];
     __shared__ uint64_t s_thr[BT];
+    __shared__ int32_t s_first[TS_TILES];
     const int tid = threadIdx.x;
     const int64_t t0 = (int64_t)blockIdx.x * TS_TILES;
     if (blockIdx.x == 0) {
@@ -317,8 +354,9 @@ __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
             a.cell_off[q] = BATCHED ? a.src_cell_off[q] : (q ? a.m_total : 0);
         }
     }
-    if (vec && (t0 + TS_TILES) * TILE <= a.n_total) tile_sums_body<BATCHED, true>(a, t0, s_wave, s_thr);
-    else tile_sums_body<BATCHED, false>(a, t0, s_wave, s_thr);
+    if (vec && (t0 + TS_TILES) * TILE <= a.n_total)
+        tile_sums_body<BATCHED, true>(a, t0, s_wave, s_thr, s_first);
+    else tile_sums_body<BATCHED, false>(a, t0, s_wave, s_thr, s_first);
 }
 
 // ---------------------------------------------------------------------------
@@ -554,12 +592,23 @@ __device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
     uint32_t wv[ITEMS];
     load_items<FULL>(a.w, i0, n, wv);
     const uint64_t tp = a.tile_prefix[t];
-    int32_t dcur = 0;
-    if (BATCHED) dcur = find_segment(a.elem_off, a.D, i0 < n ? i0 : n - 1);
+    // the distributions of the tile's elements lie in [d_lo, d_hi]
+    int32_t dcur = 0, d_lo = 0, d_hi = 0;
+    if (BATCHED) {
+        d_lo = a.tile_dist[t];
+        d_hi = a.tile_dist[t + 1];
+        dcur = find_segment_in(a.elem_off, d_lo, d_hi + 1, i0 < n ? i0 : n - 1);
+    }
     Dist P = a.dists[dcur];
     const uint64_t hw = hexists ? hraw : 0u;
     Dist HP = P;
-    if (BATCHED && tid < 64) HP = a.dists[hexists ? find_segment(a.elem_off, a.D, hi_) : 0];
+    if (BATCHED && tid < 64 && hexists) {
+        // left halo: between the previous tile's first distribution and d_lo;
+        // right halo: between d_hi and the next tile's last
+        const int32_t lo = left ? a.tile_dist[t > 0 ? t - 1 : 0] : d_hi;
+        const int32_t hi = left ? d_lo : a.tile_dist[t + 2];
+        HP = a.dists[find_segment_in(a.elem_off, lo, hi + 1, hi_)];
+    }
 
     uint64_t sum = 0;
 #pragma unroll
@@ -611,6 +660,8 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     const int64_t base = t * TILE;
     const int64_t n = a.n_total;
     const int32_t lb0 = (int32_t)(base - HALO);  // global index of local leaf 0
+    // distributions of the tile's own elements: [d_lo, d_hi]
+    const int32_t d_lo = BATCHED ? a.tile_dist[t] : 0, d_hi = BATCHED ? a.tile_dist[t + 1] : 0;
     if (tid == 0) sm.ndefer = 0;
 
     // ---- phase 1: keys and cells of the tile's leaves -----------------------
@@ -642,7 +693,7 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
             const bool dist_start = cp < 0 || (sm.key[HALO] == 0 && cp != c);
             cb = dist_start ? c : (int64_t)cp + 1;
         } else {  // the tile starts past its distribution's last positive weight
-            const Dist &P = a.dists[BATCHED ? find_segment(a.elem_off, a.D, base) : 0];
+            const Dist &P = a.dists[d_lo];
             cb = P.co + P.m;
         }
         sm.c_begin = cb;
@@ -776,7 +827,7 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
             }
             // the distribution's last leaf with mass covers the remaining cells
             if (!next_same) {
-                const Dist &P = a.dists[BATCHED ? find_segment(a.elem_off, a.D, gj) : 0];
+                const Dist &P = a.dists[BATCHED ? find_segment_in(a.elem_off, d_lo, d_hi + 1, gj) : 0];
                 const int64_t cend = P.co + P.m;
                 if (cend - cj > 1) {
                     if (cend - cj - 1 > RUN_CAP) push_run(a, cj + 1, cend, gj, kj, KEY_END);
@@ -816,24 +867,27 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
 // ---------------------------------------------------------------------------
 // k_fixup: the deferred work, from the keys in global memory
 // ---------------------------------------------------------------------------
+// The view is confined to one distribution: a subtree, a cell and a run never
+// leave it, and a leaf outside it reads as a position outside [0, n) (it can
+// be neither in the same cell nor in the same distribution).
 template <bool BATCHED>
 struct GlobalView {
     const BuildArgs &a;
-    __device__ GlobalView(const BuildArgs &args) : a(args) {}
-    __device__ int32_t dist_of(int64_t i) const {
-        return BATCHED ? find_segment(a.elem_off, a.D, i) : 0;
-    }
+    const Dist &P;
+    const int64_t e0, e1;  // the distribution's elements [e0, e1)
+    __device__ GlobalView(const BuildArgs &args, const Dist &dist)
+        : a(args), P(dist), e0(dist.eo), e1(dist.eo + dist.n) {}
     __device__ Leaf leaf(int64_t i) const {
         Leaf L;
         L.key = 0;
         L.cell = -2;
-        if (i < 0 || i >= a.n_total) return L;
+        if (i < e0 || i >= e1) return L;
         L.key = a.nodes[i].key;
         if (L.key == ~0ull) {
             L.cell = -1;
             return L;
         }
-        L.cell = cell_of_key(L.key, a.dists[dist_of(i)]);
+        L.cell = cell_of_key(L.key, P);
         return L;
     }
     __device__ int level(int64_t b) const { return level_between(leaf(b), leaf(b + 1)); }
@@ -846,11 +900,11 @@ struct GlobalView {
     }
     // smallest a <= k with in_range on [a, k] (in_range(k) holds)
     __device__ int64_t extend_left(int64_t k, uint64_t kk, int32_t c, int l) const {
-        int64_t good = k, bad = -1;
+        int64_t good = k, bad = e0 - 1;
         for (int64_t dd = 1;; dd <<= 1) {
             int64_t x = k - dd;
-            if (x < 0 || !in_range(x, kk, c, l)) {
-                bad = x < -1 ? -1 : x;
+            if (x < e0 || !in_range(x, kk, c, l)) {
+                bad = x < e0 - 1 ? e0 - 1 : x;
                 break;
             }
             good = x;
@@ -864,11 +918,11 @@ struct GlobalView {
     }
     // largest b >= k with in_range on [k, b] (in_range(k) holds)
     __device__ int64_t extend_right(int64_t k, uint64_t kk, int32_t c, int l) const {
-        int64_t good = k, bad = a.n_total;
+        int64_t good = k, bad = e1;
         for (int64_t dd = 1;; dd <<= 1) {
             int64_t x = k + dd;
-            if (x >= a.n_total || !in_range(x, kk, c, l)) {
-                bad = x > a.n_total ? a.n_total : x;
+            if (x >= e1 || !in_range(x, kk, c, l)) {
+                bad = x > e1 ? e1 : x;
                 break;
             }
             good = x;
@@ -968,13 +1022,15 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
 template <bool BATCHED>
 __device__ void fixup_tile(const BuildArgs &a, int64_t t) {
     const int32_t cnt = a.defer_count[t];
-    GlobalView<BATCHED> gv(a);
     const int64_t base = t * TILE;
+    const int32_t d_lo = BATCHED ? a.tile_dist[t] : 0, d_hi = BATCHED ? a.tile_dist[t + 1] : 0;
     // more deferrals than were kept: redo every node record of the tile
     const bool all = cnt > DEFER_CAP;
     const int64_t count = all ? (a.n_total - base < TILE ? a.n_total - base : TILE) : cnt;
     for (int64_t k = threadIdx.x; k < count; k += BT) {
         const int64_t j = all ? base + k : (int64_t)a.defer_items[t * DEFER_CAP + k];
+        const Dist &P = a.dists[BATCHED ? find_segment_in(a.elem_off, d_lo, d_hi + 1, j) : 0];
+        GlobalView<BATCHED> gv(a, P);
         uint64_t kj;
         int32_t c0, c1;
         if (gv.node(j, kj, c0, c1)) gv.root_cell(j, c1);

@@ -114,6 +114,7 @@ struct BuildArgs {
     uint64_t *dist_local;   // [D]: in-tile prefix at each distribution start
     int32_t *defer_count;   // [ntiles]
     int32_t *defer_items;   // [ntiles * DEFER_CAP]: deferred node indices
+    int32_t *tile_dist;     // [ntiles + 2]: distribution of element min(t TILE, n - 1)
     int32_t *run_count;     // chunks listed in runs
     RunChunk *runs;         // [run_chunk_cap(m_total)]
 };

@@ -17,13 +17,21 @@ namespace {
 
 constexpr int QT = 256;
 constexpr int QI = 16;
+constexpr int QMAX_LDS_DISTS = 64;  // distributions a k_qmax block sums in LDS
 
-__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
-    int32_t lo = 0, hi = D;
+// Index d with off[d] <= i < off[d+1] over off[0..D], found by the whole
+// block (uniform i): each round probes QT evenly spaced offsets at once, so
+// 10^4 distributions take two dependent loads instead of a binary search's
+// fourteen.  Every thread of the block must call it.
+__device__ inline int32_t block_find_segment(const int64_t *off, int32_t D, int64_t i) {
+    int32_t lo = 0, hi = D;  // off[lo] <= i < off[hi]
     while (hi - lo > 1) {
-        int32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= i) lo = mid;
-        else hi = mid;
+        const int32_t step = (hi - lo + QT - 1) / QT;
+        const int32_t p = lo + ((int32_t)threadIdx.x + 1) * step;
+        const int below = (p < hi && off[p] <= i) ? 1 : 0;
+        const int32_t nlo = lo + __syncthreads_count(below) * step;
+        hi = nlo + step < hi ? nlo + step : hi;
+        lo = nlo;
     }
     return lo;
 }
@@ -45,30 +53,48 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
                                              const int64_t *__restrict__ off, int32_t D,
                                              int64_t n, double *scale, uint32_t *status) {
     __shared__ uint32_t s_max[QT / 64];
+    __shared__ uint32_t s_dmax[QMAX_LDS_DISTS];
     __shared__ int s_bad;
     const int64_t b0 = (int64_t)blockIdx.x * QT * QI;
     const int64_t b1 = b0 + (int64_t)QT * QI < n ? b0 + (int64_t)QT * QI : n;
-    const int32_t dfirst = off ? find_segment(off, D, b0) : 0;
-    const bool one = !off || off[dfirst + 1] >= b1;
+    // all of the thread's loads first (clamped, in range), so that they and
+    // the search for the block's first distribution are in flight together
+    float xs[QI];
+#pragma unroll
+    for (int k = 0; k < QI; ++k) {
+        const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
+        xs[k] = v[i < n ? i : n - 1];
+    }
+    const int32_t dfirst = off ? block_find_segment(off, D, b0) : 0;
+    const int32_t dlast = off ? block_find_segment(off, D, b1 - 1) : 0;
+    const bool one = dlast == dfirst;
+    // a block over a few distributions collects their maxima in LDS and adds
+    // each to global memory once; only one over very many uses global atomics
+    const bool lds = !one && dlast - dfirst < QMAX_LDS_DISTS;
     if (threadIdx.x == 0) s_bad = 0;
+    if (lds)
+        for (int32_t q = threadIdx.x; q <= dlast - dfirst; q += QT) s_dmax[q] = 0u;
     __syncthreads();
     int32_t d = dfirst;
     int64_t dend = off ? off[d + 1] : n;
     uint32_t mx = 0;
     bool bad = false;
-#pragma unroll 4
+#pragma unroll
     for (int k = 0; k < QI; ++k) {
         const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
         if (i >= b1) break;
         if (!one) {
             while (i >= dend) {
-                if (mx) atomicMax(max_word(scale, d), mx);
+                if (mx) {
+                    if (lds) atomicMax(s_dmax + (d - dfirst), mx);
+                    else atomicMax(max_word(scale, d), mx);
+                }
                 mx = 0;
                 ++d;
                 dend = off[d + 1];
             }
         }
-        const float x = v[i];
+        const float x = xs[k];
         if (!(x >= 0.0f) || isinf(x)) {
             bad = true;
             continue;
@@ -98,8 +124,14 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
             if (s_bad && status) atomicOr(status, status_bit(RTF_ERR_VALUE));
         }
     } else {
-        if (mx) atomicMax(max_word(scale, d), mx);
+        if (mx) {
+            if (lds) atomicMax(s_dmax + (d - dfirst), mx);
+            else atomicMax(max_word(scale, d), mx);
+        }
         __syncthreads();
+        if (lds)
+            for (int32_t q = threadIdx.x; q <= dlast - dfirst; q += QT)
+                if (s_dmax[q]) atomicMax(max_word(scale, dfirst + q), s_dmax[q]);
         if (threadIdx.x == 0 && s_bad && status) atomicOr(status, status_bit(RTF_ERR_VALUE));
     }
 }
@@ -163,10 +195,16 @@ __global__ __launch_bounds__(QT) void k_qapply(const float *__restrict__ v,
                                                uint32_t *__restrict__ out) {
     const int64_t b0 = (int64_t)blockIdx.x * QT * QI;
     const int64_t b1 = b0 + (int64_t)QT * QI < n ? b0 + (int64_t)QT * QI : n;
-    int32_t d = off ? find_segment(off, D, b0) : 0;
+    float xs[QI];  // every load in flight before the distribution search
+#pragma unroll
+    for (int k = 0; k < QI; ++k) {
+        const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
+        xs[k] = v[i < n ? i : n - 1];
+    }
+    int32_t d = off ? block_find_segment(off, D, b0) : 0;
     int64_t dend = off ? off[d + 1] : n;
     double s = scale_of(scale, d);
-#pragma unroll 4
+#pragma unroll
     for (int k = 0; k < QI; ++k) {
         const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
         if (i >= b1) break;
@@ -177,7 +215,7 @@ __global__ __launch_bounds__(QT) void k_qapply(const float *__restrict__ v,
             }
             s = scale_of(scale, d);
         }
-        const float x = v[i];
+        const float x = xs[k];
         uint32_t q = 0;
         if (x > 0.0f && !isinf(x)) {
             double y = rint((double)x * s);

@@ -160,31 +160,38 @@ __global__ __launch_bounds__(256) void k_sample_2d(const Node *__restrict__ node
                                                    double *__restrict__ xy) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const Dist &M = dists[0];
+    // a pair is read with one 16-byte load and written with one 8-byte and one
+    // 16-byte store, so every wave access covers whole consecutive lines
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+    typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    const u64x2 *up = reinterpret_cast<const u64x2 *>(u2);
+    i32x2 *rcp = reinterpret_cast<i32x2 *>(rc);
+    f64x2 *xyp = reinterpret_cast<f64x2 *>(xy);
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
-        const uint64_t ur = u2[2 * s], uc = u2[2 * s + 1];
+        const u64x2 uu = __builtin_nontemporal_load(up + s);
+        const uint64_t ur = uu.x, uc = uu.y;
+        i32x2 out = {-1, -1};
+        f64x2 pos = {__builtin_nan(""), __builtin_nan("")};
         Hit hr;
         hr.i = -1;
         if (!(M.flags & DIST_ZERO)) hr = descend(nodes, cells, M, ur, n_total);
         const int64_t r = hr.i - M.eo;
         // the marginal must have one weight per row distribution 1..D-1
-        if (hr.i < 0 || 1 + r >= D) {
-            rc[2 * s] = rc[2 * s + 1] = -1;
-            if (WANT_X) xy[2 * s] = xy[2 * s + 1] = __builtin_nan("");
-            continue;
+        if (hr.i >= 0 && 1 + r < D) {
+            out.x = (int32_t)r;
+            if (WANT_X) pos.x = position(M, hr, ur);
+            const Dist &R = dists[1 + r];
+            Hit hc;
+            hc.i = -1;
+            if (!(R.flags & DIST_ZERO)) hc = descend(nodes, cells, R, uc, n_total);
+            if (hc.i >= 0) {
+                out.y = (int32_t)(hc.i - R.eo);
+                if (WANT_X) pos.y = position(R, hc, uc);
+            }
         }
-        rc[2 * s] = (int32_t)r;
-        if (WANT_X) xy[2 * s] = position(M, hr, ur);
-        const Dist &R = dists[1 + r];
-        Hit hc;
-        hc.i = -1;
-        if (!(R.flags & DIST_ZERO)) hc = descend(nodes, cells, R, uc, n_total);
-        if (hc.i < 0) {
-            rc[2 * s + 1] = -1;
-            if (WANT_X) xy[2 * s + 1] = __builtin_nan("");
-            continue;
-        }
-        rc[2 * s + 1] = (int32_t)(hc.i - R.eo);
-        if (WANT_X) xy[2 * s + 1] = position(R, hc, uc);
+        __builtin_nontemporal_store(out, rcp + s);
+        if (WANT_X) __builtin_nontemporal_store(pos, xyp + s);
     }
 }
 

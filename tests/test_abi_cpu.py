@@ -81,6 +81,15 @@ def test_argument_errors_before_launch(L):
     assert r == rtf.RTF_ERR_INVALID_ARG
     r = L.rtf_quantize_f32(None, None, 1, 10, fake, fake, None, None)
     assert r == rtf.RTF_ERR_INVALID_ARG
+    # a well-formed descriptor (never dereferenced) with misaligned pair buffers
+    f2 = rtf.rtf_forest(D=2, tile=2048, n_total=10, m_total=10, nodes=0x100000,
+                        cells=0x100000, dists=0x100000, status=0x100000)
+    r = L.rtf_sample_2d(ctypes.byref(f2), P(0x100008), 4, fake, fake, None)
+    assert r == rtf.RTF_ERR_INVALID_ARG  # u2 not 16-byte aligned
+    r = L.rtf_sample_2d(ctypes.byref(f2), fake, 4, P(0x100004), fake, None)
+    assert r == rtf.RTF_ERR_INVALID_ARG  # out_rc not 8-byte aligned
+    r = L.rtf_sample_2d(ctypes.byref(f2), fake, 4, fake, P(0x100008), None)
+    assert r == rtf.RTF_ERR_INVALID_ARG  # out_xy not 16-byte aligned
     for c in range(7):
         assert L.rtf_status_string(c).decode().startswith("RTF_")
 
