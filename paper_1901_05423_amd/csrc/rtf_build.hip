@@ -457,9 +457,7 @@ constexpr int LEAF_N = TILE + 2 * HALO;
 constexpr int LVL_N = LEAF_N - 1;  // real boundaries; lvl[LVL_N] is padding
 static_assert(LEAF_N % 8 == 0, "levels are read 8 at a time");
 static_assert(2 * HALO == 64, "wave 0 loads both halos, one leaf per lane");
-constexpr int WIN_PER_WAVE = WIN / (BT / 64);  // a wave's share of the window
-static_assert(WIN % (4 * (BT / 64)) == 0 && (LEAF_N * 12) % 16 == 0, "16-byte clears of slot and window");
-static_assert(2 * WIN_PER_WAVE >= 4 * 64 * ((LEAF_N / 4 + BT - 1) / BT), "phase 3 list fits the window share");
+static_assert(WIN % 4 == 0 && (LEAF_N * 12) % 16 == 0, "16-byte clears of slot and window");
 constexpr int32_t SLOT_EMPTY = INT32_MIN;  // never a node or leaf reference
 
 // Owner codes of the guide cells staged in the window: which local leaf a
@@ -486,8 +484,6 @@ __device__ inline void push_item(TileSmem &sm, int32_t item) {
     int32_t k = atomicAdd(&sm.ndefer, 1);
     if (k < DEFER_CAP) sm.items[k] = item;
 }
-
-__device__ inline int byte_at(uint64_t w, int p) { return (int)((w >> (8 * p)) & 0xff); }
 
 __device__ inline int lvl_at(const TileSmem &sm, int bi) {
     return (int)((sm.lvl8[bi >> 3] >> (8 * (bi & 7))) & 0xff);
@@ -669,7 +665,7 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     else build_keys<BATCHED, false>(a, sm, t);
     __syncthreads();
 
-    // ---- phase 2: levels of all boundaries held; empty child slots ---------
+    // ---- phase 2: levels of all boundaries held; empty slots and window ----
     {
         // one level per thread and byte (consecutive lanes, no bank conflicts);
         // byte bi of the array is byte bi & 7 of word bi >> 3
@@ -683,7 +679,9 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
     }
     {
         const int4 se = make_int4(SLOT_EMPTY, SLOT_EMPTY, SLOT_EMPTY, SLOT_EMPTY);
+        const int4 we = make_int4(WIN_EMPTY, WIN_EMPTY, WIN_EMPTY, WIN_EMPTY);
         for (int x = tid; x < 2 * TILE / 4; x += BT) reinterpret_cast<int4 *>(sm.slot)[x] = se;
+        for (int x = tid; x < WIN / 4; x += BT) reinterpret_cast<int4 *>(sm.win)[x] = we;
     }
     if (tid == 0) {
         // first guide cell whose record comes from a leaf of this tile
@@ -703,88 +701,67 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
 
     // ---- phase 3: parent links of the internal nodes ------------------------
     // Only a boundary inside a cell (level below SENT) is a node under
-    // another node, and the leaf children follow from three neighbouring
-    // levels (phase 4).  Each wave lists its boundaries below SENT, about a
-    // quarter of them at m = n, in its share of the guide-cell window, then
-    // takes one listed boundary per lane, so the searches run on full waves.
-    // The wave clears its share of the window afterwards for phase 4.
+    // another node; the leaf children follow from three neighbouring levels
+    // (phase 4).  Thread g takes the four boundaries 4g..4g+3 and holds the
+    // twenty levels around them as five 32-bit words.  Each boundary's
+    // nearest higher boundary on either side comes from byte-parallel
+    // compares and selects, without branches; only a subtree wider than the
+    // window scans on in LDS.
     {
-        const int wv = tid >> 6, lane = tid & 63;
-        uint16_t *list = reinterpret_cast<uint16_t *>(sm.win + wv * WIN_PER_WAVE);
-        int total = 0;  // uniform across the wave
-        for (int g0 = wv * 64; g0 < LEAF_N / 4; g0 += BT) {
-            const int g = g0 + lane;  // four boundaries 4g..4g+3
-            uint32_t fl = 0;
-            if (g < LEAF_N / 4) {
-                const uint32_t w4 = reinterpret_cast<const uint32_t *>(sm.lvl8)[g];
+        const uint32_t *lv32 = reinterpret_cast<const uint32_t *>(sm.lvl8);
+        constexpr int NW32 = LEAF_N / 4;  // 32-bit level words
+        for (int g = tid; g < NW32; g += BT) {
+            uint32_t W[5];
+            bool V[5];  // word inside the tile's level array
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (4 * g + q < LVL_N && ((w4 >> (8 * q)) & 0xff) < SENT) fl |= 1u << q;
+            for (int k = 0; k < 5; ++k) {
+                const int gi = g - 2 + k;
+                V[k] = gi >= 0 && gi < NW32;
+                W[k] = V[k] ? lv32[gi] : 0u;
             }
-            const int c = __popc(fl);
-            int incl = c;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += y;
-            }
-            int pos = total + incl - c;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (fl & (1u << q)) list[pos++] = (uint16_t)(4 * g + q);
-            total += __shfl(incl, 63, 64);
-        }
-        for (int k = lane; k < total; k += 64) {
-            const int bi = list[k];
-            const int wi = bi >> 3, p = bi & 7;
-            const bool has_l = wi > 0, has_r = wi + 1 < LEAF_N / 8;
-            const uint64_t wl = has_l ? sm.lvl8[wi - 1] : 0, wc = sm.lvl8[wi];
-            const uint64_t wr = has_r ? sm.lvl8[wi + 1] : 0;
-            const int l = byte_at(wc, p);
-            // L: nearest boundary left of bi with a level above l, in wc below
-            // byte p or else in wl (chosen by selects, one bit search); only
-            // a subtree wider than the two words scans on in LDS
-            int L, lL;
-            {
-                const uint64_t mc = ge_mask(wc, l + 1) & ((1ull << (8 * p)) - 1);
-                const uint64_t mw = has_l ? ge_mask(wl, l + 1) : 0;
-                const bool in_c = mc != 0;
-                const uint64_t mk = in_c ? mc : mw;
-                const uint64_t wsel = in_c ? wc : wl;
-                const int pos = (63 - clz64(mk | 0x80)) >> 3;  // byte 0 if mk == 0
-                L = 8 * (in_c ? wi : wi - 1) + pos;
-                lL = byte_at(wsel, pos);
-                if (mk == 0) {
-                    L = has_l ? nearest_ge_left(sm, 8 * (wi - 1) - 1, l + 1) : -1;
+            for (int q = 0; q < 4; ++q) {
+                const int bi = 4 * g + q;
+                const int l = (int)((W[2] >> (8 * q)) & 0xff);
+                const bool active = bi < LVL_N && l < SENT;
+                // L: nearest boundary left of bi with a level above l
+                const uint32_t tl = __builtin_amdgcn_perm(0u, (uint32_t)(127 - l), 0u);
+                const uint32_t m2 = ((W[2] + tl) & 0x80808080u) & ((1u << (8 * q)) - 1u);
+                const uint32_t m1 = V[1] ? (W[1] + tl) & 0x80808080u : 0u;
+                const uint32_t m0 = V[0] ? (W[0] + tl) & 0x80808080u : 0u;
+                const uint32_t mL = m2 ? m2 : (m1 ? m1 : m0);
+                const uint32_t wL = m2 ? W[2] : (m1 ? W[1] : W[0]);
+                const int kL = m2 ? 2 : (m1 ? 1 : 0);
+                const int pL = (31 - __builtin_clz(mL | 0x80u)) >> 3;
+                int L = 4 * (g - 2 + kL) + pL;
+                int lL = (int)((wL >> (8 * pL)) & 0xff);
+                // R: nearest boundary right of bi with a level at least l
+                const uint32_t tr = __builtin_amdgcn_perm(0u, (uint32_t)(128 - l), 0u);
+                const uint32_t r2 = q < 3 ? ((W[2] + tr) & 0x80808080u) & (~0u << (8 * q + 8)) : 0u;
+                const uint32_t r3 = V[3] ? (W[3] + tr) & 0x80808080u : 0u;
+                const uint32_t r4 = V[4] ? (W[4] + tr) & 0x80808080u : 0u;
+                const uint32_t mR = r2 ? r2 : (r3 ? r3 : r4);
+                const uint32_t wR = r2 ? W[2] : (r3 ? W[3] : W[4]);
+                const int kR = r2 ? 2 : (r3 ? 3 : 4);
+                const int pR = __builtin_ctz(mR | 0x80000000u) >> 3;
+                int R = 4 * (g - 2 + kR) + pR;
+                int lR = (int)((wR >> (8 * pR)) & 0xff);
+                if (active && mL == 0) {  // wider subtree: scan on left of the window
+                    L = nearest_ge_left(sm, 4 * (g - 2) - 1, l + 1);
                     lL = L >= 0 ? lvl_at(sm, L) : 0;
                 }
-            }
-            // R: nearest boundary right of bi with a level at least l, in wc
-            // above byte p or else in wr
-            int R, lR;
-            {
-                const uint64_t mc = p < 7 ? ge_mask(wc, l) & (~0ull << (8 * p + 8)) : 0;
-                const uint64_t mw = has_r ? ge_mask(wr, l) : 0;
-                const bool in_c = mc != 0;
-                const uint64_t mk = in_c ? mc : mw;
-                const uint64_t wsel = in_c ? wc : wr;
-                const int pos = __builtin_ctzll(mk | (1ull << 63)) >> 3;
-                R = 8 * (in_c ? wi : wi + 1) + pos;
-                lR = byte_at(wsel, pos);
-                if (mk == 0) {
-                    R = has_r ? nearest_ge_right(sm, 8 * (wi + 2), l) : -1;
+                if (active && mR == 0) {  // and right of it
+                    R = nearest_ge_right(sm, 4 * (g + 3), l);
                     lR = R >= 0 ? lvl_at(sm, R) : 0;
                 }
+                if (R >= LVL_N) R = -1;  // the padding byte: beyond the window
+                if (active && L >= 0 && R >= 0) {  // else the fix-up finds the parent
+                    const int32_t ref = lb0 + bi + 1;
+                    if (lL > lR) link(sm, R + 1, 0, ref);
+                    else link(sm, L + 1, 1, ref);
+                }
             }
-            if (R >= LVL_N) R = -1;       // the padding byte: beyond the window
-            if (L < 0 || R < 0) continue;  // the parent is found by the fix-up
-            const int32_t ref = lb0 + bi + 1;
-            if (lL > lR) link(sm, R + 1, 0, ref);
-            else link(sm, L + 1, 1, ref);
         }
-        const int4 we = make_int4(WIN_EMPTY, WIN_EMPTY, WIN_EMPTY, WIN_EMPTY);
-        for (int x = lane; x < WIN_PER_WAVE / 4; x += 64)
-            reinterpret_cast<int4 *>(sm.win + wv * WIN_PER_WAVE)[x] = we;
     }
     __syncthreads();
 
