@@ -57,9 +57,21 @@ struct Hit {
 // below u.  Otherwise the descent continues from the cell's tree root.  A
 // reference outside the forest, or a path longer than the forest has nodes,
 // can only come from a damaged workspace.
+__device__ inline Hit resolve(const Node *nodes, const Cell &c, const Dist &P, uint64_t u,
+                              int64_t n_total);
+
+__device__ inline int64_t cell_index(const Dist &P, uint64_t u) {
+    return P.co + (int64_t)mulhi64(u, (uint64_t)P.m);
+}
+
 __device__ inline Hit descend(const Node *nodes, const Cell *cells, const Dist &P, uint64_t u,
                               int64_t n_total) {
-    const Cell c = load_cell(cells, P.co + (int64_t)mulhi64(u, (uint64_t)P.m));
+    return resolve(nodes, load_cell(cells, cell_index(P, u)), P, u, n_total);
+}
+
+// The sample's leaf from its cell record c (and, past the record, the tree).
+__device__ inline Hit resolve(const Node *nodes, const Cell &c, const Dist &P, uint64_t u,
+                              int64_t n_total) {
     Hit h;
     if (c.ref < 0) {  // one interval covers the cell
         h.i = ~(int64_t)c.ref;
@@ -158,40 +170,64 @@ __global__ __launch_bounds__(256) void k_sample_2d(const Node *__restrict__ node
                                                    const uint64_t *__restrict__ u2, int64_t S,
                                                    int32_t *__restrict__ rc,
                                                    double *__restrict__ xy) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const Dist &M = dists[0];
-    // a pair is read with one 16-byte load and written with one 8-byte and one
-    // 16-byte store, so every wave access covers whole consecutive lines
     typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
     typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
     typedef double f64x2 __attribute__((ext_vector_type(2)));
+    // a pair is read with one 16-byte load and written with one 8-byte and one
+    // 16-byte store, so every wave access covers whole consecutive lines; a
+    // lane takes two pairs at a time (s and s + T) and issues the loads of
+    // each step of both chains (row record, row parameters, column record)
+    // together, two dependent chains in flight instead of one
     const u64x2 *up = reinterpret_cast<const u64x2 *>(u2);
     i32x2 *rcp = reinterpret_cast<i32x2 *>(rc);
     f64x2 *xyp = reinterpret_cast<f64x2 *>(xy);
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
-        const u64x2 uu = __builtin_nontemporal_load(up + s);
-        const uint64_t ur = uu.x, uc = uu.y;
-        i32x2 out = {-1, -1};
-        f64x2 pos = {__builtin_nan(""), __builtin_nan("")};
-        Hit hr;
-        hr.i = -1;
-        if (!(M.flags & DIST_ZERO)) hr = descend(nodes, cells, M, ur, n_total);
-        const int64_t r = hr.i - M.eo;
-        // the marginal must have one weight per row distribution 1..D-1
-        if (hr.i >= 0 && 1 + r < D) {
-            out.x = (int32_t)r;
-            if (WANT_X) pos.x = position(M, hr, ur);
-            const Dist &R = dists[1 + r];
-            Hit hc;
-            hc.i = -1;
-            if (!(R.flags & DIST_ZERO)) hc = descend(nodes, cells, R, uc, n_total);
-            if (hc.i >= 0) {
-                out.y = (int32_t)(hc.i - R.eo);
-                if (WANT_X) pos.y = position(R, hc, uc);
-            }
+    const int64_t T = (int64_t)gridDim.x * blockDim.x;
+    const Dist &M = dists[0];
+    const bool mzero = (M.flags & DIST_ZERO) != 0;
+    for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s0 < S; s0 += 2 * T) {
+        int64_t s[2] = {s0, s0 + T};
+        bool ok[2] = {true, s0 + T < S};
+        u64x2 uu[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) uu[k] = ok[k] ? __builtin_nontemporal_load(up + s[k]) : u64x2{0, 0};
+        Cell cr[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) cr[k] = load_cell(cells, cell_index(M, uu[k].x));
+        Hit hr[2];
+        int64_t r[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            hr[k].i = -1;
+            if (!mzero) hr[k] = resolve(nodes, cr[k], M, uu[k].x, n_total);
+            r[k] = hr[k].i - M.eo;
+            // the marginal must have one weight per row distribution 1..D-1
+            if (hr[k].i < 0 || 1 + r[k] >= D) r[k] = -1;
         }
-        __builtin_nontemporal_store(out, rcp + s);
-        if (WANT_X) __builtin_nontemporal_store(pos, xyp + s);
+        Dist R[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) R[k] = dists[r[k] >= 0 ? 1 + r[k] : 0];
+        Cell cc[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) cc[k] = load_cell(cells, cell_index(R[k], uu[k].y));
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (!ok[k]) continue;
+            i32x2 out = {-1, -1};
+            f64x2 pos = {__builtin_nan(""), __builtin_nan("")};
+            if (r[k] >= 0) {
+                out.x = (int32_t)r[k];
+                if (WANT_X) pos.x = position(M, hr[k], uu[k].x);
+                Hit hc;
+                hc.i = -1;
+                if (!(R[k].flags & DIST_ZERO)) hc = resolve(nodes, cc[k], R[k], uu[k].y, n_total);
+                if (hc.i >= 0) {
+                    out.y = (int32_t)(hc.i - R[k].eo);
+                    if (WANT_X) pos.y = position(R[k], hc, uu[k].y);
+                }
+            }
+            __builtin_nontemporal_store(out, rcp + s[k]);
+            if (WANT_X) __builtin_nontemporal_store(pos, xyp + s[k]);
+        }
     }
 }
 
