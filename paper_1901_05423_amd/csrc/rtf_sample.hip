@@ -8,15 +8,23 @@ namespace rtf {
 
 namespace {
 
-__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
-    int32_t lo = 0, hi = D;
+// Index d with off[d] <= i < off[d+1] over off[0..D], found by a whole block
+// of 256 threads (uniform i): each round probes 256 evenly spaced offsets, so
+// 10^4 distributions take two dependent loads.  Every thread must call it.
+__device__ inline int32_t block_find_segment(const int64_t *off, int32_t D, int64_t i) {
+    int32_t lo = 0, hi = D;  // off[lo] <= i < off[hi]
     while (hi - lo > 1) {
-        int32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= i) lo = mid;
-        else hi = mid;
+        const int32_t step = (hi - lo + 255) / 256;
+        const int32_t p = lo + ((int32_t)threadIdx.x + 1) * step;
+        const int below = (p < hi && off[p] <= i) ? 1 : 0;
+        const int32_t nlo = lo + __syncthreads_count(below) * step;
+        hi = nlo + step < hi ? nlo + step : hi;
+        lo = nlo;
     }
     return lo;
 }
+
+constexpr int SCHUNK = 256 * 8;  // samples per block step of the batched kernel
 
 __device__ inline Node load_node(const Node *nodes, int64_t j) {
     uint4 v = *reinterpret_cast<const uint4 *>(nodes + j);
@@ -144,10 +152,7 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
                                                 const uint64_t *__restrict__ u, int64_t S,
                                                 int32_t *__restrict__ idx,
                                                 double *__restrict__ x) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride) {
-        const int32_t d = BATCHED ? find_segment(sample_off, D, s) : 0;
-        const Dist &P = dists[d];
+    auto one = [&](int64_t s, const Dist &P) {
         const uint64_t us = __builtin_nontemporal_load(u + s);
         Hit h;
         h.i = -1;
@@ -155,10 +160,30 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
         if (h.i < 0) {
             idx[s] = -1;
             if (WANT_X) x[s] = __builtin_nan("");
-            continue;
+            return;
         }
         __builtin_nontemporal_store((int32_t)(h.i - P.eo), idx + s);
         if (WANT_X) __builtin_nontemporal_store(position(P, h, us), x + s);
+    };
+    if (!BATCHED) {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride)
+            one(s, dists[0]);
+        return;
+    }
+    // batched: a block takes chunks of SCHUNK consecutive samples, finds the
+    // chunk's first distribution once (block-wide), and each lane steps on
+    // through the few distributions the chunk spans
+    for (int64_t c0 = (int64_t)blockIdx.x * SCHUNK; c0 < S; c0 += (int64_t)gridDim.x * SCHUNK) {
+        int32_t d = block_find_segment(sample_off, D, c0);
+        int64_t dend = sample_off[d + 1];
+#pragma unroll
+        for (int k = 0; k < SCHUNK / 256; ++k) {
+            const int64_t s = c0 + threadIdx.x + 256 * k;
+            if (s >= S) break;
+            while (s >= dend) dend = sample_off[++d + 1];
+            one(s, dists[d]);
+        }
     }
 }
 
@@ -298,8 +323,8 @@ hipError_t launch_sample(const Node *nodes, const Cell *cells, const Dist *dists
                          const int64_t *sample_off, int32_t D, int64_t n_total,
                          const uint64_t *u, int64_t S, int32_t *idx, double *x,
                          hipStream_t st) {
-    const dim3 g(grid_for(S)), b(256);
     const bool batched = sample_off != nullptr;
+    const dim3 g(batched ? grid_for((S + SCHUNK / 256 - 1) / (SCHUNK / 256)) : grid_for(S)), b(256);
     if (batched && x)
         hipLaunchKernelGGL((k_sample<true, true>), g, b, 0, st, nodes, cells, dists, sample_off,
                            D, n_total, u, S, idx, x);
