@@ -174,6 +174,15 @@ def test_2d_small_map(rtf, orc):
     check_2d(rtf, orc, img, marg, 200000, 3, zero_rows=True)
 
 
+def test_2d_two_pairs_per_lane(rtf, orc):
+    """More pairs than the sampling grid has lanes (4M), an odd count: every
+    lane takes two interleaved pairs per step and the last step is ragged."""
+    note("2D 64x300, 9M pairs")
+    from paper_1901_05423_amd import workloads as wl
+    img, marg = wl.map_2d(np.random.default_rng(41), rows=64, cols=300, spots=2)
+    check_2d(rtf, orc, img, marg, 9_000_001, 5)
+
+
 def test_c3_2d_full_map(rtf, orc):
     """4096 x 4096 log-normal(0, 1.5) map with 8 hot spots: forest of the
     marginal plus 4096 rows bit-exact, 2^20 pairs checked."""
