@@ -27,24 +27,36 @@ namespace rtf {
 // small device helpers
 // ---------------------------------------------------------------------------
 
+// Lane i receives lane i - k's value under the DPP row control CTRL (0 where
+// the source lies outside the row or the row is masked off), for both halves.
+template <int CTRL, int ROW_MASK>
+__device__ inline uint64_t dpp_move(uint64_t x) {
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)x, CTRL, ROW_MASK, 0xf, false);
+    const uint32_t hi =
+        __builtin_amdgcn_update_dpp(0u, (uint32_t)(x >> 32), CTRL, ROW_MASK, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive scan over the 64 lanes with DPP moves (no LDS round trips):
+// row_shr 1, 2, 4, 8 scan each row of 16 lanes, then row_bcast 15 adds row 0's
+// total to row 1 (and row 2's to row 3) and row_bcast 31 adds lanes 0..31's
+// total to rows 2 and 3.
 __device__ inline uint64_t wave_incl_scan(uint64_t x) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint64_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    x += dpp_move<0x111, 0xf>(x);  // row_shr:1
+    x += dpp_move<0x112, 0xf>(x);  // row_shr:2
+    x += dpp_move<0x114, 0xf>(x);  // row_shr:4
+    x += dpp_move<0x118, 0xf>(x);  // row_shr:8
+    x += dpp_move<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_move<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
     return x;
 }
 
+// Inclusive suffix sum over the 64 lanes: the wave total (lane 63's prefix)
+// minus the prefix before the lane.
 __device__ inline uint64_t wave_incl_suffix(uint64_t x) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint64_t y = __shfl_down(x, o, 64);
-        if (lane + o < 64) x += y;
-    }
-    return x;
+    const uint64_t incl = wave_incl_scan(x);
+    const uint64_t total = __shfl(incl, 63, 64);
+    return total - incl + x;
 }
 
 // Exclusive scan over the block (NW waves); returns the thread's exclusive
@@ -485,8 +497,10 @@ __device__ inline void push_item(TileSmem &sm, int32_t item) {
     if (k < DEFER_CAP) sm.items[k] = item;
 }
 
+// the level of local boundary bi: byte bi of the level array (one LDS byte
+// read, no shift)
 __device__ inline int lvl_at(const TileSmem &sm, int bi) {
-    return (int)((sm.lvl8[bi >> 3] >> (8 * (bi & 7))) & 0xff);
+    return reinterpret_cast<const uint8_t *>(sm.lvl8)[bi];
 }
 
 // bit 7 of every byte of w (eight levels, each < 128) that is >= t, for
