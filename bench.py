@@ -84,9 +84,10 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--profile", action="store_true",
                    help="few steps, no baselines (for rocprofv3 runs)")
-    p.add_argument("--config", choices=["h24", "c3", "c4", "c5"], default="h24",
+    p.add_argument("--config", choices=["h24", "c3", "c4", "c5", "table1"], default="h24",
                    help="h24: the benchmark line; c3/c4/c5: the 2D map, the uneven batch and "
-                        "the differentiable workload (extra measurements)")
+                        "the differentiable workload; table1: load counts and speed on the "
+                        "paper's high-dynamic-range densities (extra measurements)")
     return p.parse_args()
 
 
@@ -117,6 +118,83 @@ def sample_bytes_model(key, child, table, K, aux, m, u):
         float(visits[deeper].mean()) if deeper.any() else 0.0, float(1.0 - deeper.mean())
 
 
+def loads_forest_alg2(key, child, table, m, u):
+    """Alg. 2 load by load, as the paper counts it: the guide entry, then one
+    node record per step until a leaf."""
+    g = ((u.astype(object) * m) >> 64).astype(np.int64)
+    j = table[g].astype(np.int64)
+    loads = np.ones(u.size, np.int64)
+    active = j >= 0
+    while active.any():
+        ja = j[active]
+        loads[active] += 1
+        j[active] = np.where(u[active] < key[ja], child[ja, 0], child[ja, 1])
+        active = j >= 0
+    return loads
+
+
+def loads_forest_records(key, child, table, K, aux, m, u):
+    """This library's lookup: the 64-byte cell record, and only when it does
+    not resolve the sample, the node records of the descent plus the key pair
+    of the position."""
+    g = ((u.astype(object) * m) >> 64).astype(np.int64)
+    ref = table[g].astype(np.int64)
+    ax = aux[g].astype(np.int64)
+    deeper = (ref >= 0) & (ax >= 0) & (u >= K[g, 6])
+    j = np.where(deeper, ax, -1).astype(np.int64)
+    visits = np.zeros(u.size, np.int64)
+    active = j >= 0
+    while active.any():
+        ja = j[active]
+        visits[active] += 1
+        j[active] = np.where(u[active] < key[ja], child[ja, 0], child[ja, 1])
+        active = j >= 0
+    return 1 + deeper * (visits + 1)
+
+
+def loads_bisection(key, lo, hi, u):
+    """Key loads of the bisection the baselines run on [lo, hi]."""
+    MAX = np.uint64(2 ** 64 - 1)
+    a, b = lo.astype(np.int64).copy(), hi.astype(np.int64) + 1
+    cnt = np.zeros(u.size, np.int64)
+    act = b - a > 1
+    while act.any():
+        mid = a + (b - a) // 2
+        k = key[np.minimum(mid, key.size - 1)]
+        go = (k != MAX) & (k <= u)
+        a = np.where(act & go, mid, a)
+        b = np.where(act & ~go, mid, b)
+        cnt += act
+        act = b - a > 1
+    return cnt
+
+
+def loads_cutpoint(key, table, m, u):
+    """The Cutpoint Method with bisection (Sec. 2.5): the guide entry, then a
+    bisection between the cell's first overlapping interval and the next
+    cell's."""
+    n = key.size
+    g = ((u.astype(object) * m) >> 64).astype(np.int64)
+    r0 = table[g].astype(np.int64)
+    r1 = np.where(g + 1 < m, table[np.minimum(g + 1, m - 1)].astype(np.int64), n - 1)
+    covered = r0 < 0
+    lo = np.where(covered, ~r0, np.maximum(r0 - 1, 0))
+    hi = np.where(covered, ~r0, np.where(g + 1 < m, np.where(r1 < 0, ~r1, r1), n - 1))
+    hi = np.maximum(hi, lo)
+    return 1 + loads_bisection(key, lo, hi, u)
+
+
+def load_stats(loads):
+    """Maximum, average, and the average over groups of 32 and 64 consecutive
+    samples of each group's maximum (a synchronised group waits for its
+    slowest member)."""
+    def group(G):
+        k = (loads.size // G) * G
+        return float(loads[:k].reshape(-1, G).max(axis=1).mean())
+    return {"max": int(loads.max()), "avg": float(loads.mean()), "avg32": group(32),
+            "avg64": group(64)}
+
+
 def timed(fn, start, stop, reps):
     ts = []
     for _ in range(reps):
@@ -135,7 +213,7 @@ def main():
               "one distribution is built and sampled on a single device", file=sys.stderr)
         sys.exit(2)
     if args.config != "h24":
-        {"c3": run_c3, "c4": run_c4, "c5": run_c5}[args.config](args)
+        {"c3": run_c3, "c4": run_c4, "c5": run_c5, "table1": run_table1}[args.config](args)
         return
     import torch
     import paper_1901_05423_amd as rtf
@@ -326,6 +404,55 @@ def common(metric, unit, value, ms, args, dtype, workload, **extra):
            "config": {"workload": workload}}
     out.update(extra)
     return out
+
+
+def run_table1(args):
+    """The densities of the paper's load-count table (p ~ i^20,
+    (i mod 32 + 1)^25, (i mod 64 + 1)^35) at n = 2^log2n with m = n (or
+    --cell-ratio): loads per sample replayed on the host for Alg. 2 as
+    printed, for this library's record lookup and for the Cutpoint Method
+    with bisection (maximum, average, average over 32 and 64 synchronised
+    lanes), and samples/s of the three on the GPU."""
+    import torch
+    import paper_1901_05423_amd as rtf
+    from paper_1901_05423_amd import workloads as wl
+    dev = torch.device("cuda:0")
+    n = 1 << (args.log2n if args.log2n != 24 else 20)
+    S = 1 << args.log2s
+    ratio = args.cell_ratio if args.cell_ratio is not None else 1.0
+    m = max(1, int(round(ratio * n)))
+    r = wl.rng(wl.TABLE1)
+    u_h = wl.uniforms(r, S)
+    u = torch.from_numpy(u_h).to(dev)
+    idx = torch.empty(S, dtype=torch.int32, device=dev)
+    x = torch.empty(S, dtype=torch.float64, device=dev)
+    sub = u_h[: 1 << 20]
+    out = {}
+    for fam in wl.TABLE1_FAMILIES:
+        v = torch.from_numpy(wl.table1_weights(fam, n)).to(dev)
+        q, _ = rtf.quantize(v)
+        f = rtf.build(q, m)
+        f.check()
+        t_b = event_time(lambda: rtf.build(q, m, ws=f.ws), args.steps)
+        t_s = event_time(lambda: rtf.sample(f, u, out=(idx, x)), args.steps)
+        t_bs = event_time(lambda: rtf.sample_bsearch(f, u, out=(idx, x)), args.steps)
+        t_cb = event_time(lambda: rtf.sample_cutpoint_bsearch(f, u, out=(idx, x)), args.steps)
+        key, child, table, W, (K, aux) = f.export(with_cells=True)
+        out[fam] = {
+            "loads_cutpoint_bisection": load_stats(loads_cutpoint(key, table, m, sub)),
+            "loads_forest_alg2": load_stats(loads_forest_alg2(key, child, table, m, sub)),
+            "loads_forest_records": load_stats(loads_forest_records(key, child, table, K, aux, m,
+                                                                    sub)),
+            "samples_s": {"forest": S / (t_s * 1e-3), "cutpoint_bisection": S / (t_cb * 1e-3),
+                          "binary_search": S / (t_bs * 1e-3)},
+            "build_ms": t_b,
+        }
+    res = common(METRIC, "samples/s", out[wl.TABLE1_FAMILIES[0]]["samples_s"]["forest"],
+                 S / out[wl.TABLE1_FAMILIES[0]]["samples_s"]["forest"] * 1e3, args, "u64",
+                 f"Table-1 densities p~i^20, (i mod 32+1)^25, (i mod 64+1)^35 at n=2^{int(np.log2(n))}, "
+                 f"m={ratio:g}n, S=2^{args.log2s}; loads replayed on 2^20 of the uniforms",
+                 families=out)
+    print(json.dumps(res), flush=True)
 
 
 def batch_ratio(args):

@@ -23,6 +23,7 @@ C4_BATCHED = 4
 C5_DIFF = 5
 H24_UNIFORM = 24
 H24_ZIPF = 25
+TABLE1 = 30  # uniforms for the load-count families
 
 
 def rng(config_id: int) -> np.random.Generator:
@@ -92,3 +93,22 @@ def batched_uneven(r: np.random.Generator, D: int = 10000, lo: int = 16,
 def logits(r: np.random.Generator, D: int = 256, n: int = 4096) -> np.ndarray:
     """N(0, 1) float32 logits, shape [D, n]."""
     return r.standard_normal((D, n)).astype(np.float32)
+
+
+# The three densities of the paper's load-count table (Sec. 6), with index
+# i = 0 .. n-1; each is normalised to a maximum of 1 in FP64 before the cast
+# to float32, so values below float32's range become zero weights.
+TABLE1_FAMILIES = ("pow20", "mod32_pow25", "mod64_pow35")
+
+
+def table1_weights(family: str, n: int) -> np.ndarray:
+    i = np.arange(n, dtype=np.float64)
+    if family == "pow20":  # p_i ~ i^20
+        w = (i / max(n - 1, 1)) ** 20
+    elif family == "mod32_pow25":  # p_i ~ (i mod 32 + 1)^25
+        w = ((np.mod(i, 32) + 1) / 32.0) ** 25
+    elif family == "mod64_pow35":  # p_i ~ (i mod 64 + 1)^35
+        w = ((np.mod(i, 64) + 1) / 64.0) ** 35
+    else:
+        raise ValueError(family)
+    return w.astype(np.float32)

@@ -255,3 +255,15 @@ def test_deferral_overflow(rtf, orc):
         w[a:a + 3000] = 0
     build_and_compare(rtf, orc, w, 4, S_extra=20000, seed=3)
     build_and_compare(rtf, orc, w, 40000, S_extra=20000, seed=4)
+
+
+@pytest.mark.parametrize("family", ["pow20", "mod32_pow25", "mod64_pow35"])
+def test_table1_densities(rtf, orc, family):
+    """The high-dynamic-range densities of the paper's load-count table,
+    quantised: bit-exact forest and samples at m = n and m = n/4."""
+    from paper_1901_05423_amd import workloads as wl
+    note(f"table-1 density {family} n=65536")
+    n = 1 << 16
+    q, _ = orc.quantize(wl.table1_weights(family, n))
+    build_and_compare(rtf, orc, q, n, S_extra=40000, seed=11)
+    build_and_compare(rtf, orc, q, n // 4, S_extra=40000, seed=12)
