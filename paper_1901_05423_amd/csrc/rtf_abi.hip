@@ -49,7 +49,7 @@ Layout make_layout(int32_t D, int64_t n, int64_t m) {
     L.ditems = o;
     o = align256(o + sizeof(int32_t) * (size_t)L.ntiles * DEFER_CAP);
     L.runs = o;
-    o = align256(o + sizeof(RunChunk) * (size_t)run_chunk_cap(m));
+    o = align256(o + sizeof(Run) * (size_t)run_cap(m));
     L.total = o;
     return L;
 }
@@ -111,8 +111,8 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     a.tile_dist = reinterpret_cast<int32_t *>(b + L.tdist);
     a.defer_count = reinterpret_cast<int32_t *>(b + L.dcnt);
     a.defer_items = reinterpret_cast<int32_t *>(b + L.ditems);
-    a.run_count = reinterpret_cast<int32_t *>(b + L.status + 64);  // in the status block
-    a.runs = reinterpret_cast<RunChunk *>(b + L.runs);
+    a.run_count = reinterpret_cast<uint64_t *>(b + L.status + 64);  // in the status block
+    a.runs = reinterpret_cast<Run *>(b + L.runs);
     if (launch_build(a, st) != hipSuccess) return RTF_ERR_HIP;
     *out = f;
     return RTF_OK;

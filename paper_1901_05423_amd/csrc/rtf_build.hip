@@ -227,26 +227,26 @@ __device__ inline void root_record(Cell *cells, int64_t g, int32_t a, uint64_t k
 }
 
 // List the guide-table run [lo, hi), covered by interval i with keys k0 and
-// k1, in chunks of FILL_CH cells for the fix-up kernel.
+// k1, for the fix-up kernel.  One 64-bit atomic takes both the list slot and
+// the run's offset in the sequence of listed cells, so offsets grow with the
+// slot.
 __device__ inline void push_run(const BuildArgs &a, int64_t lo, int64_t hi, int32_t i, uint64_t k0,
                                 uint64_t k1) {
-    const int32_t nch = (int32_t)((hi - lo + FILL_CH - 1) / FILL_CH);
-    const int32_t first = atomicAdd(a.run_count, nch);
-    const int64_t cap = run_chunk_cap(a.m_total);
-    for (int32_t q = 0; q < nch; ++q) {
-        if (first + q >= cap) {  // impossible by the bound of run_chunk_cap
-            atomicOr(a.status, status_bit(RTF_ERR_WORKSPACE));
-            return;
-        }
-        RunChunk r;
-        r.k0 = k0;
-        r.k1 = k1;
-        r.lo = (int32_t)(lo + (int64_t)q * FILL_CH);
-        r.hi = (int32_t)(hi < lo + (int64_t)(q + 1) * FILL_CH ? hi : lo + (int64_t)(q + 1) * FILL_CH);
-        r.i = i;
-        r.pad = 0;
-        a.runs[first + q] = r;
+    const uint64_t len = (uint64_t)(hi - lo);
+    const uint64_t old = atomicAdd((unsigned long long *)a.run_count, (1ull << 32) | len);
+    const int64_t slot = (int64_t)(old >> 32);
+    if (slot >= run_cap(a.m_total)) {  // impossible by the bound of run_cap
+        atomicOr(a.status, status_bit(RTF_ERR_WORKSPACE));
+        return;
     }
+    Run r;
+    r.k0 = k0;
+    r.k1 = k1;
+    r.lo = (int32_t)lo;
+    r.len = (int32_t)len;
+    r.i = i;
+    r.off = (uint32_t)old;
+    a.runs[slot] = r;
 }
 
 __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t c0, int32_t c1) {
@@ -858,6 +858,41 @@ __global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
 // ---------------------------------------------------------------------------
 // k_fixup: the deferred work, from the keys in global memory
 // ---------------------------------------------------------------------------
+// Wave-wide search for the end of a run: pred(d) holds for 0 <= d <= D and
+// fails for d > D; d past `lim` counts as failing without being evaluated.
+// pred(0) must hold.  The lanes probe 64 distances per step, first galloping
+// (strides 1, 64, 4096, ...) and then cutting the bracket 64-fold per step.
+// Every lane returns D.
+template <class Pred>
+__device__ inline int64_t wave_run(Pred pred, int64_t lim) {
+    const int64_t lane = threadIdx.x & 63;
+    int64_t good = 0, bad = 0, s = 1;
+    for (;;) {
+        const int64_t d = good + s * (lane + 1);
+        const uint64_t fail = __ballot(!(d <= lim && pred(d)));
+        if (fail == 0) {
+            good += 64 * s;
+            s *= 64;
+            continue;
+        }
+        const int64_t f = __builtin_ctzll(fail);
+        bad = good + s * (f + 1);
+        bad = bad < lim + 1 ? bad : lim + 1;  // the refinement probes only d < bad
+        good += s * f;
+        break;
+    }
+    while (bad - good > 1) {
+        const int64_t step = (bad - good + 63) / 64;
+        const int64_t d = good + step * (lane + 1);  // lane 63 reaches bad
+        const uint64_t fail = __ballot(!(d < bad && pred(d)));
+        const int64_t f = __builtin_ctzll(fail);
+        const int64_t nb = good + step * (f + 1);
+        good += step * f;
+        bad = nb < bad ? nb : bad;
+    }
+    return good;
+}
+
 // The view is confined to one distribution: a subtree, a cell and a run never
 // leave it, and a leaf outside it reads as a position outside [0, n) (it can
 // be neither in the same cell nor in the same distribution).
@@ -963,6 +998,42 @@ struct GlobalView {
         c1 = root(j, hi);
         return false;
     }
+    // The same record computed by one whole wave for one node j (j uniform
+    // across the wave): each search probes 64 positions per step, so a
+    // subtree range of D leaves costs about 2 log64 D dependent loads in
+    // place of 2 log2 D.
+    __device__ bool node_wave(int64_t j, uint64_t &kj, int32_t &c0, int32_t &c1) const {
+        Leaf Lj = leaf(j);
+        kj = Lj.key;
+        c0 = c1 = ~(int32_t)j;
+        if (Lj.cell < 0) return false;
+        Leaf Lp = leaf(j - 1);
+        int l = level_between(Lp, Lj);
+        if (l == SENT) {
+            c0 = (Lj.key == 0) ? ~(int32_t)j : ~(int32_t)(j - 1);
+            const int64_t b = j + wave_run([&](int64_t d) { return in_range(j + d, Lj.key, Lj.cell, 64); }, e1 - 1 - j);
+            c1 = root_wave(j, b);
+            return true;
+        }
+        const int64_t k = j - 1;
+        const int64_t lo = k - wave_run([&](int64_t d) { return in_range(k - d, Lp.key, Lp.cell, l); }, k - e0);
+        const int64_t hi =
+            (l == 0) ? j : j + wave_run([&](int64_t d) { return in_range(j + d, Lp.key, Lp.cell, l); }, e1 - 1 - j);
+        c0 = root_wave(lo, k);
+        c1 = root_wave(j, hi);
+        return false;
+    }
+    __device__ int32_t root_wave(int64_t lo, int64_t hi) const {
+        if (lo == hi) return ~(int32_t)lo;
+        const uint64_t klo = a.nodes[lo].key, khi = a.nodes[hi].key;
+        const int lam = level_of(klo, khi);
+        if (lam == 0) return (int32_t)hi;
+        const int bit = lam - 1;
+        // keys of [lo, hi] share the bits above `bit`, so the bit is clear on
+        // a prefix of the range and set on the rest
+        const int64_t D = wave_run([&](int64_t d) { return ((a.nodes[lo + d].key >> bit) & 1) == 0; }, hi - lo - 1);
+        return (int32_t)(lo + D + 1);
+    }
     // the guide cell record of the cell whose first node is j
     __device__ void root_cell(int64_t j, int32_t c1) const {
         uint64_t key[CELL_BOUNDS + 1];
@@ -982,31 +1053,100 @@ template <bool BATCHED>
 __device__ void fixup_tile(const BuildArgs &a, int64_t t);
 
 // Each block takes a contiguous range of tiles and reads their deferral
-// counts in parallel; most tiles defer nothing, so a few hundred blocks cost
-// less than one block per tile.  Then all blocks fill the listed guide-table
-// run chunks, one chunk per block at a time.
+// counts in parallel; most tiles defer nothing.  The listed nodes of all the
+// range's tiles are gathered in LDS and fixed together: one wave per node
+// while they are few (the searches then take 64 probes per step), one
+// thread per node otherwise.  A tile that kept no list redoes all its nodes,
+// one thread each.  Then every wave of the grid fills an equal share of the
+// cells of the listed guide-table runs.
+constexpr int ITEM_CAP = 1024;
+constexpr int WAVE_ITEMS = 32;
 template <bool BATCHED>
 __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
+    constexpr int NW = BT / 64;
+    __shared__ int32_t s_item[ITEM_CAP], s_itile[ITEM_CAP];
     __shared__ int32_t s_list[BT];
-    __shared__ int32_t s_n;
+    __shared__ uint64_t s_wave[NW];
+    __shared__ int32_t s_n, s_nt;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     const int64_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
     const int64_t t_lo = (int64_t)blockIdx.x * per;
     const int64_t t_hi = t_lo + per < a.ntiles ? t_lo + per : a.ntiles;
     for (int64_t t0 = t_lo; t0 < t_hi; t0 += BT) {
-        if (threadIdx.x == 0) s_n = 0;
+        if (tid == 0) {
+            s_n = 0;
+            s_nt = 0;
+        }
+        const int64_t t = t0 + tid;
+        const int32_t cnt = t < t_hi ? a.defer_count[t] : 0;
+        const int32_t listed = cnt <= DEFER_CAP ? cnt : 0;
+        uint64_t total;
+        const int64_t at = (int64_t)block_excl_scan<NW>((uint64_t)listed, s_wave, total);  // has barriers
+        if (cnt > DEFER_CAP || (listed > 0 && at + listed > ITEM_CAP)) {
+            s_list[atomicAdd(&s_nt, 1)] = tid;
+        } else if (listed > 0) {
+            for (int32_t q = 0; q < listed; ++q) {
+                s_item[at + q] = a.defer_items[t * DEFER_CAP + q];
+                s_itile[at + q] = (int32_t)(t - t0);
+            }
+            atomicMax(&s_n, (int32_t)(at + listed));
+        }
         __syncthreads();
-        const int64_t t = t0 + threadIdx.x;
-        if (t < t_hi && a.defer_count[t] != 0) s_list[atomicAdd(&s_n, 1)] = (int32_t)threadIdx.x;
-        __syncthreads();
-        const int32_t nl = s_n;
-        for (int32_t q = 0; q < nl; ++q) fixup_tile<BATCHED>(a, t0 + s_list[q]);
+        const int32_t ni = s_n, nt = s_nt;
+        if (ni <= WAVE_ITEMS) {
+            for (int32_t q = wid; q < ni; q += NW) {
+                const int64_t j = s_item[q], tq = t0 + s_itile[q];
+                const Dist &P = a.dists[BATCHED ? find_segment_in(a.elem_off, a.tile_dist[tq], a.tile_dist[tq + 1] + 1, j) : 0];
+                GlobalView<BATCHED> gv(a, P);
+                uint64_t kj;
+                int32_t c0, c1;
+                const bool first = gv.node_wave(j, kj, c0, c1);
+                if (lane == 0) {
+                    if (first) gv.root_cell(j, c1);
+                    store_node(a.nodes, j, kj, c0, c1);
+                }
+            }
+        } else {
+            for (int32_t q = tid; q < ni; q += BT) {
+                const int64_t j = s_item[q], tq = t0 + s_itile[q];
+                const Dist &P = a.dists[BATCHED ? find_segment_in(a.elem_off, a.tile_dist[tq], a.tile_dist[tq + 1] + 1, j) : 0];
+                GlobalView<BATCHED> gv(a, P);
+                uint64_t kj;
+                int32_t c0, c1;
+                if (gv.node(j, kj, c0, c1)) gv.root_cell(j, c1);
+                store_node(a.nodes, j, kj, c0, c1);
+            }
+        }
+        for (int32_t q = 0; q < nt; ++q) fixup_tile<BATCHED>(a, t0 + s_list[q]);
         __syncthreads();
     }
-    const int64_t cap = run_chunk_cap(a.m_total);
-    const int64_t nrun = *a.run_count < cap ? *a.run_count : cap;
-    for (int64_t k = blockIdx.x; k < nrun; k += gridDim.x) {
-        const RunChunk r = a.runs[k];
-        for (int64_t c = r.lo + threadIdx.x; c < r.hi; c += BT) store_covered(a.cells, c, r.k0, r.k1, r.i);
+    // the listed cells [0, total) in equal contiguous shares, one per wave
+    const uint64_t rc = *a.run_count;
+    const int64_t cap = run_cap(a.m_total);
+    const int64_t nrun = (int64_t)(rc >> 32);
+    const int64_t total = nrun > 0 && nrun <= cap ? (int64_t)(uint32_t)rc : 0;  // else flagged
+    const int64_t nwaves = (int64_t)gridDim.x * NW, gw = (int64_t)blockIdx.x * NW + wid;
+    int64_t p = total * gw / nwaves;
+    const int64_t p_end = total * (gw + 1) / nwaves;
+    if (p >= p_end) return;
+    // the last run whose offset is at most p (runs[0].off = 0)
+    int64_t r = wave_run([&](int64_t d) { return (int64_t)a.runs[d].off <= p; }, nrun - 1);
+    // the records as a flat array of 16-byte words, so that one store of the
+    // wave writes 1 KiB in a row: lane l always writes word l % 4 of a record
+    // (keys k0 and k1, zeros, zeros, then zero, ref and aux)
+    uint4 *words = reinterpret_cast<uint4 *>(a.cells);
+    while (p < p_end) {
+        const Run R = a.runs[r];
+        const int64_t e = (int64_t)R.off + R.len < p_end ? (int64_t)R.off + R.len : p_end;
+        const uint32_t ni = ~(uint32_t)R.i;
+        const uint4 v = (lane & 3) == 0   ? make_uint4((uint32_t)R.k0, (uint32_t)(R.k0 >> 32), (uint32_t)R.k1,
+                                                       (uint32_t)(R.k1 >> 32))
+                        : (lane & 3) == 3 ? make_uint4(0u, 0u, ni, ni)
+                                          : make_uint4(0u, 0u, 0u, 0u);
+        const int64_t w1 = 4 * ((int64_t)R.lo + (e - (int64_t)R.off));
+        for (int64_t w = 4 * ((int64_t)R.lo + (p - (int64_t)R.off)) + lane; w < w1; w += 64) words[w] = v;
+        p = e;
+        ++r;
     }
 }
 
@@ -1036,7 +1176,7 @@ hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
     const bool vec = (reinterpret_cast<uintptr_t>(a.w) & 15) == 0;
     const dim3 grid((unsigned)a.ntiles);
     const dim3 sumgrid((unsigned)((a.ntiles + TS_TILES - 1) / TS_TILES));
-    const dim3 fixgrid((unsigned)(a.ntiles < 512 ? a.ntiles : 512));
+    const dim3 fixgrid((unsigned)(a.ntiles < 1024 ? a.ntiles : 1024));
     if (a.D > 1) {
         hipLaunchKernelGGL(k_tile_sums<true>, sumgrid, dim3(BT), 0, st, a, vec);
         hipLaunchKernelGGL(k_dist_params<true>, dim3(1), dim3(PT), 0, st, a);

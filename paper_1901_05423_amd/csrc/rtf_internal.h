@@ -26,10 +26,9 @@ constexpr int WIN = TILE + 128;
 constexpr int HALO = 32;
 // Longest in-LDS subtree scan; longer ones are finished by the fix-up kernel.
 constexpr int SCAN_CAP = 64;
-// Longest guide-table run written by one lane; a longer run is listed in
-// chunks of FILL_CH cells that all blocks of the fix-up kernel fill together.
+// Longest guide-table run written by one lane; a longer run is listed for the
+// fix-up kernel, whose waves split the listed runs' cells evenly.
 constexpr int RUN_CAP = 64;
-constexpr int FILL_CH = 4096;
 // Deferred node records kept per tile; more make the fix-up redo the tile.
 constexpr int DEFER_CAP = 128;
 
@@ -62,19 +61,18 @@ struct alignas(64) Cell {
 };
 constexpr uint64_t KEY_END = ~0ull;
 
-// A chunk of a guide-table run: cells [lo, hi) are all covered by interval i,
-// whose keys are k0 and k1.
-struct alignas(16) RunChunk {
+// A listed guide-table run: cells [lo, lo + len) are all covered by interval
+// i, whose keys are k0 and k1.  `off` is the number of cells of the runs
+// listed before it, so the listed cells form one sequence [0, total).
+struct alignas(32) Run {
     uint64_t k0, k1;
-    int32_t lo, hi, i, pad;
+    int32_t lo, len, i;
+    uint32_t off;
 };
 
-// Capacity of the chunk list for m cells.  Runs longer than RUN_CAP cells are
-// disjoint, so there are at most m / (RUN_CAP + 1) of them, and a run of L
-// cells has ceil(L / FILL_CH) <= L / FILL_CH + 1 chunks.
-__host__ __device__ inline int64_t run_chunk_cap(int64_t m) {
-    return m / FILL_CH + m / (RUN_CAP + 1) + 2;
-}
+// Capacity of the run list for m cells: listed runs are longer than RUN_CAP
+// cells and disjoint.
+__host__ __device__ inline int64_t run_cap(int64_t m) { return m / (RUN_CAP + 1) + 1; }
 
 // Per-distribution parameters, written by the build's scan kernel.
 struct alignas(64) Dist {
@@ -115,8 +113,8 @@ struct BuildArgs {
     int32_t *defer_count;   // [ntiles]
     int32_t *defer_items;   // [ntiles * DEFER_CAP]: deferred node indices
     int32_t *tile_dist;     // [ntiles + 2]: distribution of element min(t TILE, n - 1)
-    int32_t *run_count;     // chunks listed in runs
-    RunChunk *runs;         // [run_chunk_cap(m_total)]
+    uint64_t *run_count;    // (runs listed << 32) | cells they cover
+    Run *runs;              // [run_cap(m_total)]
 };
 
 // ---- exact 64-bit fixed-point helpers ----------------------------------

@@ -243,6 +243,10 @@ def test_single_tree_large(rtf, orc):
     w = random_weights(rng, 300000, skew=True)
     build_and_compare(rtf, orc, w, 1, S_extra=50000, seed=1)
     build_and_compare(rtf, orc, w, 2, S_extra=50000, seed=2)
+    # a few hundred trees: tiles with a handful of deferred nodes (fixed by
+    # whole waves) beside tiles with dozens (fixed one thread per node)
+    build_and_compare(rtf, orc, w, 64, S_extra=20000, seed=5)
+    build_and_compare(rtf, orc, w, 600, S_extra=20000, seed=6)
 
 
 def test_deferral_overflow(rtf, orc):
