@@ -18,12 +18,13 @@ namespace rtf {
 
 namespace {
 
-constexpr int BB = 256;
-constexpr int CHUNK = BB * 256;  // samples per scatter block
-constexpr int LBINS = 4096;      // bins a block can sum in LDS (2 x 32 KB)
+constexpr int BB = 256;           // threads of the zeroing and combining kernels
+constexpr int SB = 1024;          // threads of a scatter block
+constexpr int ILP = 2;            // samples a scatter thread loads at once
+constexpr int CHUNK = SB * 128;   // samples per scatter block
+constexpr int LBINS = 4096;       // bins a block can sum in LDS (2 x 32 KB)
 
-__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
-    int32_t lo = 0, hi = D;
+__device__ inline int32_t find_segment_in(const int64_t *off, int32_t lo, int32_t hi, int64_t i) {
     while (hi - lo > 1) {
         int32_t mid = (lo + hi) >> 1;
         if (off[mid] <= i) lo = mid;
@@ -41,6 +42,7 @@ __global__ void k_bzero(double *B, double *Dv, int64_t n, double *A, int32_t D) 
     }
 }
 
+template <int NT>
 __device__ inline double block_sum(double x, double *s_red) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -49,81 +51,151 @@ __device__ inline double block_sum(double x, double *s_red) {
     __syncthreads();
     double t = 0.0;
     if (threadIdx.x == 0)
-        for (int i = 0; i < BB / 64; ++i) t += s_red[i];
+        for (int i = 0; i < NT / 64; ++i) t += s_red[i];
     __syncthreads();
     return t;  // valid in thread 0
 }
 
+// The samples [c0, c1) of one scatter block, ILP per thread and step, SB
+// apart: all their stream loads are issued, then all their key loads, before
+// any arithmetic, since the kernel is bound by the latency of these two
+// dependent rounds (64 KB of LDS bins leave room for two blocks per CU).
+// UNI: the block's samples all belong to distribution d0, whose parameters
+// then stay in scalar registers.  acc accumulates a xi for distribution acc_d
+// and is flushed to A when the distribution changes.
+template <bool UNI>
+__device__ inline void scatter_samples(const Node *__restrict__ nodes, const Dist *__restrict__ dists,
+                                       const int64_t *__restrict__ soff, const uint64_t *__restrict__ u,
+                                       const int32_t *__restrict__ idx, const double *__restrict__ gx,
+                                       const double *__restrict__ scale, int64_t c0, int64_t c1,
+                                       int32_t d0, int32_t d_last, bool priv, double *s_b, double *s_d,
+                                       double *B, double *Dv, double *A, double &acc, int32_t &acc_d) {
+    int32_t d = d0;  // distribution of the thread's latest sample
+    int64_t dend = UNI ? c1 : soff[d + 1];
+    // the parameters are copied into registers: read through a reference they
+    // would be fetched again after every atomic, one round trip each
+    const Dist P0 = dists[d0];
+    const double sc0 = scale[d0];
+    for (int64_t s0 = c0 + threadIdx.x; s0 < c1; s0 += (int64_t)ILP * SB) {
+        int32_t li[ILP], dq[ILP];
+        uint64_t us[ILP];
+        double g[ILP];
+        // every load is unconditional (indices clamped into range), so that
+        // all of them are in flight before the first wait
+#pragma unroll
+        for (int q = 0; q < ILP; ++q) {
+            const int64_t s = s0 + (int64_t)q * SB;
+            const int64_t sc = s < c1 ? s : c1 - 1;
+            li[q] = idx[sc];
+            us[q] = u[sc];
+            g[q] = gx[sc];
+        }
+#pragma unroll
+        for (int q = 0; q < ILP; ++q) {
+            const int64_t s = s0 + (int64_t)q * SB;
+            if (s >= c1) li[q] = -1;
+            if (!UNI && s < c1 && s >= dend) {
+                d = find_segment_in(soff, d, d_last + 1, s);
+                dend = soff[d + 1];
+            }
+            dq[q] = UNI ? d0 : d;
+        }
+        uint64_t k0[ILP], k1[ILP];
+        Dist Pq[ILP];
+        double sq[ILP];
+#pragma unroll
+        for (int q = 0; q < ILP; ++q) {
+            Pq[q] = UNI ? P0 : dists[dq[q]];
+            sq[q] = UNI ? sc0 : scale[dq[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < ILP; ++q) {
+            const Dist &P = Pq[q];
+            const bool valid = li[q] >= 0 && li[q] < P.n && !(P.flags & DIST_ZERO);
+            const int64_t lc = valid ? li[q] : 0;
+            const bool last = lc + 1 >= P.n;
+            const int64_t i = P.eo + lc;
+            k0[q] = nodes[i].key;
+            const uint64_t kn = nodes[last ? i : i + 1].key;
+            k1[q] = last ? ~0ull : kn;
+            if (!valid) li[q] = -1;
+        }
+        // the arithmetic runs for every sample (a skipped one yields values
+        // that are discarded), which keeps the compiler from sinking the
+        // loads above into the branch and waiting on them there
+#pragma unroll
+        for (int q = 0; q < ILP; ++q) {
+            const Dist &P = Pq[q];
+            const uint64_t W = P.W;
+            const uint64_t Ci = mulhi64(k0[q], W);
+            const uint64_t Cn = k1[q] != ~0ull ? mulhi64(k1[q], W) : W;
+            const uint64_t t = mulhi64(us[q], W), lo = us[q] * W;
+            const double wi = (double)(Cn - Ci);
+            const double frac = ((double)(t - Ci) + ldexp((double)lo, -64)) / wi;
+            const double xi = ldexp((double)us[q], -64);
+            const double a = g[q] / ((double)P.n * (wi / sq[q]));
+            const bool ok = li[q] >= 0;
+            if (!UNI && ok && dq[q] != acc_d) {
+                if (acc != 0.0) unsafeAtomicAdd(A + acc_d, acc);
+                acc = 0.0;
+                acc_d = dq[q];
+            }
+            acc += ok ? a * xi : 0.0;
+            if (!ok) continue;
+            if (priv) {
+                atomicAdd(s_b + li[q], a);
+                atomicAdd(s_d + li[q], a * frac);
+            } else {
+                const int64_t i = P.eo + li[q];
+                unsafeAtomicAdd(B + i, a);
+                unsafeAtomicAdd(Dv + i, a * frac);
+            }
+        }
+    }
+}
+
 template <bool BATCHED>
-__global__ __launch_bounds__(BB) void k_bscatter(const Node *__restrict__ nodes,
-                                                 const Dist *__restrict__ dists, int32_t D,
-                                                 const int64_t *__restrict__ soff,
-                                                 const uint64_t *__restrict__ u,
-                                                 const int32_t *__restrict__ idx,
-                                                 const double *__restrict__ gx, int64_t S,
-                                                 const double *__restrict__ scale, double *B,
-                                                 double *Dv, double *A) {
-    __shared__ double s_red[BB / 64];
+__global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void k_bscatter(
+    const Node *__restrict__ nodes, const Dist *__restrict__ dists, int32_t D,
+    const int64_t *__restrict__ soff, const uint64_t *__restrict__ u, const int32_t *__restrict__ idx,
+    const double *__restrict__ gx, int64_t S, const double *__restrict__ scale, double *B, double *Dv,
+    double *A) {
+    __shared__ double s_red[SB / 64];
     __shared__ double s_b[LBINS], s_d[LBINS];
-    const int64_t c0 = (int64_t)blockIdx.x * CHUNK;
+    // chunks numbered per XCD: the 8 or so blocks of one distribution share
+    // one L2 for its keys
+    const int64_t c0 = xcd_block() * CHUNK;
     const int64_t c1 = c0 + CHUNK < S ? c0 + CHUNK : S;
-    const int32_t d_first = BATCHED ? find_segment(soff, D, c0) : 0;
-    const int32_t d_last = BATCHED ? find_segment(soff, D, c1 - 1) : 0;
+    const int32_t d_first = BATCHED ? find_segment_in(soff, 0, D, c0) : 0;
+    const int32_t d_last = BATCHED ? find_segment_in(soff, d_first, D, c1 - 1) : 0;
     const bool uniform = d_first == d_last;
     const int64_t n_first = dists[d_first].n;
     const bool priv = uniform && n_first <= LBINS;  // uniform across the block
     if (priv) {
-        for (int64_t k = threadIdx.x; k < n_first; k += BB) s_b[k] = s_d[k] = 0.0;
+        for (int64_t k = threadIdx.x; k < n_first; k += SB) s_b[k] = s_d[k] = 0.0;
         __syncthreads();
     }
-    int32_t d = d_first;
-    int64_t dend = BATCHED ? soff[d + 1] : S;
+    int32_t acc_d = d_first;
     double acc = 0.0;
-    for (int64_t s = c0 + threadIdx.x; s < c1; s += BB) {
-        if (BATCHED && s >= dend) {
-            if (acc != 0.0) unsafeAtomicAdd(A + d, acc);
-            acc = 0.0;
-            d = find_segment(soff, D, s);
-            dend = soff[d + 1];
-        }
-        const int32_t li = idx[s];
-        const Dist &P = dists[d];
-        if (li < 0 || li >= P.n || (P.flags & DIST_ZERO)) continue;
-        const int64_t i = P.eo + li;
-        const uint64_t W = P.W, us = u[s];
-        const uint64_t Ci = mulhi64(nodes[i].key, W);
-        uint64_t Cn = W;
-        if (i + 1 < P.eo + P.n) {
-            const uint64_t k1 = nodes[i + 1].key;
-            if (k1 != ~0ull) Cn = mulhi64(k1, W);
-        }
-        const uint64_t t = mulhi64(us, W), lo = us * W;
-        const double wi = (double)(Cn - Ci);
-        const double frac = ((double)(t - Ci) + ldexp((double)lo, -64)) / wi;
-        const double xi = ldexp((double)us, -64);
-        const double a = gx[s] / ((double)P.n * (wi / scale[d]));
-        acc += a * xi;
-        if (priv) {
-            atomicAdd(s_b + li, a);
-            atomicAdd(s_d + li, a * frac);
-        } else {
-            unsafeAtomicAdd(B + i, a);
-            unsafeAtomicAdd(Dv + i, a * frac);
-        }
-    }
+    if (uniform)
+        scatter_samples<true>(nodes, dists, soff, u, idx, gx, scale, c0, c1, d_first, d_last, priv, s_b, s_d,
+                              B, Dv, A, acc, acc_d);
+    else
+        scatter_samples<false>(nodes, dists, soff, u, idx, gx, scale, c0, c1, d_first, d_last, priv, s_b,
+                               s_d, B, Dv, A, acc, acc_d);
     if (priv) {
         __syncthreads();
         const int64_t eo = dists[d_first].eo;
-        for (int64_t k = threadIdx.x; k < n_first; k += BB) {
+        for (int64_t k = threadIdx.x; k < n_first; k += SB) {
             if (s_b[k] != 0.0) unsafeAtomicAdd(B + eo + k, s_b[k]);
             if (s_d[k] != 0.0) unsafeAtomicAdd(Dv + eo + k, s_d[k]);
         }
     }
     if (uniform) {
-        const double t = block_sum(acc, s_red);
+        const double t = block_sum<SB>(acc, s_red);
         if (threadIdx.x == 0 && t != 0.0) unsafeAtomicAdd(A + d_first, t);
     } else if (acc != 0.0) {
-        unsafeAtomicAdd(A + d, acc);
+        unsafeAtomicAdd(A + acc_d, acc);
     }
 }
 
@@ -180,10 +252,10 @@ hipError_t launch_backward(const Node *nodes, const Dist *dists, int32_t D, int6
     if (S > 0) {
         const int64_t nb = (S + CHUNK - 1) / CHUNK;
         if (sample_off)
-            hipLaunchKernelGGL(k_bscatter<true>, dim3((unsigned)nb), dim3(BB), 0, st, nodes, dists,
+            hipLaunchKernelGGL(k_bscatter<true>, dim3((unsigned)nb), dim3(SB), 0, st, nodes, dists,
                                D, sample_off, u, idx, gx, S, scale, wsB, wsDv, wsA);
         else
-            hipLaunchKernelGGL(k_bscatter<false>, dim3((unsigned)nb), dim3(BB), 0, st, nodes, dists,
+            hipLaunchKernelGGL(k_bscatter<false>, dim3((unsigned)nb), dim3(SB), 0, st, nodes, dists,
                                D, sample_off, u, idx, gx, S, scale, wsB, wsDv, wsA);
     }
     hipLaunchKernelGGL(k_bcombine, dim3((unsigned)D), dim3(BB), 0, st, dists, wsB, wsDv, wsA,

@@ -167,6 +167,18 @@ __host__ __device__ inline uint64_t fixed_point_key(uint64_t C, uint64_t d, uint
 // Level of the boundary between two neighbouring leaves: 64 - clz(a ^ b).
 __host__ __device__ inline int level_of(uint64_t a, uint64_t b) { return 64 - clz64(a ^ b); }
 
+// The blocks of a launch are dispatched to the 8 XCDs in turn (block b to XCD
+// b mod 8), and each XCD has its own L2.  xcd_block() renumbers the blocks so
+// that each XCD's blocks carry consecutive numbers (a bijection on
+// [0, gridDim.x)): work handed out in contiguous ranges of the new number
+// then keeps neighbouring ranges, and the data they share, on one XCD.
+constexpr int NXCD = 8;
+__device__ inline int64_t xcd_block() {
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t q = G / NXCD, r = G % NXCD, x = b % NXCD;
+    return x * q + (x < r ? x : r) + b / NXCD;
+}
+
 // ---- launchers (defined in the .hip files) ----------------------------------
 
 hipError_t launch_build(const BuildArgs &a, hipStream_t st);

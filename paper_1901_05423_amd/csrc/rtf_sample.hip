@@ -171,18 +171,61 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
             one(s, dists[0]);
         return;
     }
-    // batched: a block takes chunks of SCHUNK consecutive samples, finds the
-    // chunk's first distribution once (block-wide), and each lane steps on
-    // through the few distributions the chunk spans
-    for (int64_t c0 = (int64_t)blockIdx.x * SCHUNK; c0 < S; c0 += (int64_t)gridDim.x * SCHUNK) {
-        int32_t d = block_find_segment(sample_off, D, c0);
+    // batched: a block takes chunks of SCHUNK consecutive samples (numbered
+    // per XCD, so that one XCD's L2 serves a few neighbouring distributions),
+    // finds the chunk's first distribution once (block-wide), and each lane
+    // steps on through the few distributions the chunk spans, two samples
+    // 256 apart at a time with both samples' loads issued together.  A chunk
+    // inside one distribution keeps its parameters in scalar registers.
+    auto store = [&](int64_t s, const Dist &P, const Hit &h, uint64_t us) {
+        if (h.i < 0) {
+            idx[s] = -1;
+            if (WANT_X) x[s] = __builtin_nan("");
+            return;
+        }
+        __builtin_nontemporal_store((int32_t)(h.i - P.eo), idx + s);
+        if (WANT_X) __builtin_nontemporal_store(position(P, h, us), x + s);
+    };
+    // two samples whose parameters are Pa and Pb, taken by value: through a
+    // reference the fields would be fetched again after the stores
+    auto two = [&](int64_t sa, int64_t sb, bool has_b, const Dist Pa, const Dist Pb) {
+        const uint64_t ua = __builtin_nontemporal_load(u + sa);
+        const uint64_t ub = __builtin_nontemporal_load(u + (has_b ? sb : sa));  // no branch
+        const bool za = Pa.flags & DIST_ZERO, zb = Pb.flags & DIST_ZERO;
+        const Cell ca = load_cell(cells, za ? 0 : cell_index(Pa, ua));
+        const Cell cb = load_cell(cells, zb ? 0 : cell_index(Pb, ub));
+        Hit ha, hb;
+        ha.i = hb.i = -1;
+        if (!za) ha = resolve(nodes, ca, Pa, ua, n_total);
+        if (!zb) hb = resolve(nodes, cb, Pb, ub, n_total);
+        store(sa, Pa, ha, ua);
+        if (has_b) store(sb, Pb, hb, ub);
+    };
+    for (int64_t c0 = xcd_block() * SCHUNK; c0 < S; c0 += (int64_t)gridDim.x * SCHUNK) {
+        int32_t d = __builtin_amdgcn_readfirstlane(block_find_segment(sample_off, D, c0));
         int64_t dend = sample_off[d + 1];
+        const int64_t cend = c0 + SCHUNK < S ? c0 + SCHUNK : S;
+        if (dend >= cend) {
+            // the chunk lies in one distribution: its parameters are uniform
+            const Dist P = dists[d];
 #pragma unroll
-        for (int k = 0; k < SCHUNK / 256; ++k) {
-            const int64_t s = c0 + threadIdx.x + 256 * k;
-            if (s >= S) break;
-            while (s >= dend) dend = sample_off[++d + 1];
-            one(s, dists[d]);
+            for (int k = 0; k < SCHUNK / 256; k += 2) {
+                const int64_t sa = c0 + threadIdx.x + 256 * k, sb = sa + 256;
+                if (sa >= cend) break;
+                two(sa, sb, sb < cend, P, P);
+            }
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < SCHUNK / 256; k += 2) {
+            const int64_t sa = c0 + threadIdx.x + 256 * k, sb = sa + 256;
+            if (sa >= S) break;
+            while (sa >= dend) dend = sample_off[++d + 1];
+            const int32_t da = d;
+            const bool has_b = sb < S;
+            if (has_b)
+                while (sb >= dend) dend = sample_off[++d + 1];
+            two(sa, sb, has_b, dists[da], dists[d]);
         }
     }
 }
