@@ -68,8 +68,8 @@ __device__ inline void scatter_samples(const Node *__restrict__ nodes, const Dis
                                        const int64_t *__restrict__ soff, const uint64_t *__restrict__ u,
                                        const int32_t *__restrict__ idx, const double *__restrict__ gx,
                                        const double *__restrict__ scale, int64_t c0, int64_t c1,
-                                       int32_t d0, int32_t d_last, bool priv, double *s_b, double *s_d,
-                                       double *B, double *Dv, double *A, double &acc, int32_t &acc_d) {
+                                       int32_t d0, int32_t d_last, double *B, double *Dv, double *A,
+                                       double &acc, int32_t &acc_d) {
     int32_t d = d0;  // distribution of the thread's latest sample
     int64_t dend = UNI ? c1 : soff[d + 1];
     // the parameters are copied into registers: read through a reference they
@@ -142,14 +142,61 @@ __device__ inline void scatter_samples(const Node *__restrict__ nodes, const Dis
             }
             acc += ok ? a * xi : 0.0;
             if (!ok) continue;
-            if (priv) {
-                atomicAdd(s_b + li[q], a);
-                atomicAdd(s_d + li[q], a * frac);
-            } else {
-                const int64_t i = P.eo + li[q];
-                unsafeAtomicAdd(B + i, a);
-                unsafeAtomicAdd(Dv + i, a * frac);
-            }
+            const int64_t i = P.eo + li[q];
+            unsafeAtomicAdd(B + i, a);
+            unsafeAtomicAdd(Dv + i, a * frac);
+        }
+    }
+}
+
+// A block whose samples all belong to distribution P with n <= LBINS
+// elements.  The low 32 bits of its partial sums C_k are staged in LDS
+// (C_k = floor(U_k W / 2^64), and W for the trailing zero weights whose key
+// is all ones): for the sampled i, 0 <= t - C_i < w_i < 2^32, so 32-bit
+// differences give t - C_i and w_i = C_{i+1} - C_i exactly, and no sample
+// reads a key from L2.  B and D are summed in LDS bins and added to global
+// memory once per bin.
+__device__ inline void scatter_local(const Node *__restrict__ nodes, const Dist P, double sc,
+                                     const uint64_t *__restrict__ u, const int32_t *__restrict__ idx,
+                                     const double *__restrict__ gx, int64_t c0, int64_t c1, double *s_b,
+                                     double *s_d, uint32_t *s_clo, double &acc) {
+    const int64_t n = P.n;
+    for (int64_t k = threadIdx.x; k < n; k += SB) {
+        const uint64_t key = nodes[P.eo + k].key;
+        s_clo[k] = (uint32_t)(key == ~0ull ? P.W : mulhi64(key, P.W));
+        s_b[k] = s_d[k] = 0.0;
+    }
+    __syncthreads();
+    if (P.flags & DIST_ZERO) return;  // no sample of it has an index
+    const uint32_t w_lo = (uint32_t)P.W;
+    for (int64_t s0 = c0 + threadIdx.x; s0 < c1; s0 += (int64_t)ILP * SB) {
+        int32_t li[ILP];
+        uint64_t us[ILP];
+        double g[ILP];
+#pragma unroll
+        for (int q = 0; q < ILP; ++q) {
+            const int64_t s = s0 + (int64_t)q * SB;
+            const int64_t sc_ = s < c1 ? s : c1 - 1;
+            li[q] = idx[sc_];
+            us[q] = u[sc_];
+            g[q] = gx[sc_];
+        }
+#pragma unroll
+        for (int q = 0; q < ILP; ++q) {
+            const int64_t s = s0 + (int64_t)q * SB;
+            const bool ok = s < c1 && li[q] >= 0 && li[q] < n;
+            const int32_t lc = ok ? li[q] : 0;
+            const uint32_t ci = s_clo[lc];
+            const uint32_t cn = lc + 1 < n ? s_clo[lc + 1] : w_lo;
+            const uint64_t t = mulhi64(us[q], P.W), lo = us[q] * P.W;
+            const double wi = (double)(uint32_t)(cn - ci);
+            const double frac = ((double)(uint32_t)((uint32_t)t - ci) + ldexp((double)lo, -64)) / wi;
+            const double xi = ldexp((double)us[q], -64);
+            const double a = g[q] / ((double)n * (wi / sc));
+            acc += ok ? a * xi : 0.0;
+            if (!ok) continue;
+            atomicAdd(s_b + lc, a);
+            atomicAdd(s_d + lc, a * frac);
         }
     }
 }
@@ -160,35 +207,35 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const int64_t *__restrict__ soff, const uint64_t *__restrict__ u, const int32_t *__restrict__ idx,
     const double *__restrict__ gx, int64_t S, const double *__restrict__ scale, double *B, double *Dv,
     double *A) {
-    __shared__ double s_red[SB / 64];
+    // 80 KB, so that two blocks fit in a CU's 160 KB; the block sum reuses
+    // the staged partial sums' space
     __shared__ double s_b[LBINS], s_d[LBINS];
+    __shared__ uint32_t s_clo[LBINS];
+    double *s_red = reinterpret_cast<double *>(s_clo);
     // chunks numbered per XCD: the 8 or so blocks of one distribution share
-    // one L2 for its keys
+    // one L2
     const int64_t c0 = xcd_block() * CHUNK;
     const int64_t c1 = c0 + CHUNK < S ? c0 + CHUNK : S;
     const int32_t d_first = BATCHED ? find_segment_in(soff, 0, D, c0) : 0;
     const int32_t d_last = BATCHED ? find_segment_in(soff, d_first, D, c1 - 1) : 0;
     const bool uniform = d_first == d_last;
-    const int64_t n_first = dists[d_first].n;
-    const bool priv = uniform && n_first <= LBINS;  // uniform across the block
-    if (priv) {
-        for (int64_t k = threadIdx.x; k < n_first; k += SB) s_b[k] = s_d[k] = 0.0;
-        __syncthreads();
-    }
+    const Dist P0 = dists[d_first];
+    const bool local = uniform && P0.n <= LBINS;  // uniform across the block
     int32_t acc_d = d_first;
     double acc = 0.0;
-    if (uniform)
-        scatter_samples<true>(nodes, dists, soff, u, idx, gx, scale, c0, c1, d_first, d_last, priv, s_b, s_d,
-                              B, Dv, A, acc, acc_d);
+    if (local)
+        scatter_local(nodes, P0, scale[d_first], u, idx, gx, c0, c1, s_b, s_d, s_clo, acc);
+    else if (uniform)
+        scatter_samples<true>(nodes, dists, soff, u, idx, gx, scale, c0, c1, d_first, d_last, B, Dv, A, acc,
+                              acc_d);
     else
-        scatter_samples<false>(nodes, dists, soff, u, idx, gx, scale, c0, c1, d_first, d_last, priv, s_b,
-                               s_d, B, Dv, A, acc, acc_d);
-    if (priv) {
-        __syncthreads();
-        const int64_t eo = dists[d_first].eo;
-        for (int64_t k = threadIdx.x; k < n_first; k += SB) {
-            if (s_b[k] != 0.0) unsafeAtomicAdd(B + eo + k, s_b[k]);
-            if (s_d[k] != 0.0) unsafeAtomicAdd(Dv + eo + k, s_d[k]);
+        scatter_samples<false>(nodes, dists, soff, u, idx, gx, scale, c0, c1, d_first, d_last, B, Dv, A, acc,
+                               acc_d);
+    __syncthreads();
+    if (local) {
+        for (int64_t k = threadIdx.x; k < P0.n; k += SB) {
+            if (s_b[k] != 0.0) unsafeAtomicAdd(B + P0.eo + k, s_b[k]);
+            if (s_d[k] != 0.0) unsafeAtomicAdd(Dv + P0.eo + k, s_d[k]);
         }
     }
     if (uniform) {

@@ -263,6 +263,57 @@ def test_grad_uneven_raw(rtf, orc):
     torch.cuda.synchronize()
 
 
+def raw_grad(rtf, orc, vs, counts, seed):
+    """rtf_backward on distributions vs with counts[d] uniforms each, every
+    distribution against the oracle."""
+    import torch
+    rng = np.random.default_rng(seed)
+    v = np.concatenate(vs).astype(np.float32)
+    eo = offsets([x.size for x in vs])
+    so = offsets(counts)
+    u = rng.integers(0, 2 ** 64, int(so[-1]), dtype=np.uint64)
+    g = rng.standard_normal(int(so[-1]))
+    eod = to_dev(eo)
+    if len(vs) > 1:
+        q, s = rtf.quantize(to_dev(v), eod)
+        f = rtf.build_batched(q, eod, eod)
+        sod = to_dev(so)
+        ud = to_dev(u)
+        idx, _ = rtf.sample_batched(f, sod, ud)
+        gw = rtf.backward(f, ud, idx, to_dev(g), s, sample_off=sod).cpu().numpy()
+    else:
+        q, s = rtf.quantize(to_dev(v))
+        f = rtf.build(q, v.size)
+        ud = to_dev(u)
+        idx, _ = rtf.sample(f, ud)
+        gw = rtf.backward(f, ud, idx, to_dev(g), s).cpu().numpy()
+    q_h, s_h = q.cpu().numpy(), s.cpu().numpy()
+    for d in range(len(vs)):
+        a, b = eo[d], eo[d + 1]
+        ref = orc.grad(q_h[a:b], s_h[d], u[so[d]:so[d + 1]], g[so[d]:so[d + 1]])
+        scale = max(np.abs(ref).max(), 1.0)
+        assert np.abs(gw[a:b] - ref).max() <= 1e-9 * scale, d
+    torch.cuda.synchronize()
+
+
+def test_grad_block_paths(rtf, orc):
+    """The three ways a scatter block runs: samples of one distribution of at
+    most 4096 weights (partial sums staged in LDS, here with zero runs and
+    trailing zeros, whose keys are all ones), of one larger distribution
+    (keys read per sample), and of several distributions."""
+    note("grad block paths")
+    rng = np.random.default_rng(43)
+    small = (0.01 + rng.random(3000)).astype(np.float32)
+    small[500:700] = 0
+    small[-40:] = 0
+    raw_grad(rtf, orc, [small], [300000], 1)
+    big = (0.01 + rng.random(10000)).astype(np.float32)
+    big[-3:] = 0
+    raw_grad(rtf, orc, [big], [300000], 2)
+    mixed = [small, big, (0.5 + rng.random(100)).astype(np.float32), np.ones(4096, np.float32)]
+    raw_grad(rtf, orc, mixed, [262149, 140000, 7, 131072], 3)
+
+
 def test_c5_grad_full(rtf, orc):
     """256 distributions of 4096 softplus(N(0,1)) weights, 2^20 uniforms each,
     L = sum sin(7x): dL/dlogits of 4 distributions checked against the oracle."""
