@@ -583,7 +583,8 @@ def run_c5(args):
     so = torch.arange(D + 1, dtype=torch.int64, device=dev) * per
     v = torch.nn.functional.softplus(z).reshape(-1).contiguous()
     from paper_1901_05423_amd.plan import BatchedPlan
-    plan = BatchedPlan(eo, eo, so, D * nd, D * nd, D * per)
+    co = torch.arange(D + 1, dtype=torch.int64, device=dev) * (nd // 4)
+    plan = BatchedPlan(eo, co, so, D * nd, D * (nd // 4), D * per)
     plan.run(v, u)
     plan.check()
     f = plan
@@ -599,7 +600,7 @@ def run_c5(args):
     t_bwd = event_time(bwd, args.steps)
     S = D * per
     res = common(METRIC, "samples/s", S / ((t_fwd + t_bwd) * 1e-3), t_fwd + t_bwd, args, "u64",
-                 "C5: 256 distributions x 4096 softplus(N(0,1)) weights, 2^20 uniforms each; "
+                 "C5: 256 distributions x 4096 softplus(N(0,1)) weights, m_d=0.25n_d, 2^20 uniforms each; "
                  "forward quantise + build + sample with x, backward dL/dw of L = sum sin(7x)",
                  ms_forward=t_fwd, ms_backward=t_bwd,
                  forward_samples_s=S / (t_fwd * 1e-3), backward_samples_s=S / (t_bwd * 1e-3))

@@ -165,7 +165,7 @@ rtf_status rtf_sample(const rtf_forest *f, const uint64_t *u, int64_t S, int32_t
     if (S == 0) return RTF_OK;
     return from_hip(launch_sample(static_cast<const Node *>(f->nodes),
                                   static_cast<const Cell *>(f->cells),
-                                  static_cast<const Dist *>(f->dists), nullptr, 1, f->n_total, u, S,
+                                  static_cast<const Dist *>(f->dists), nullptr, 1, f->n_total, f->m_total, u, S,
                                   out_idx, out_x, stream));
 }
 
@@ -177,7 +177,7 @@ rtf_status rtf_sample_batched(const rtf_forest *f, const int64_t *sample_off, co
     return from_hip(launch_sample(static_cast<const Node *>(f->nodes),
                                   static_cast<const Cell *>(f->cells),
                                   static_cast<const Dist *>(f->dists), sample_off, f->D, f->n_total,
-                                  u, S, out_idx, out_x, stream));
+                                  f->m_total, u, S, out_idx, out_x, stream));
 }
 
 rtf_status rtf_sample_2d(const rtf_forest *f, const uint64_t *u2, int64_t S, int32_t *out_rc,

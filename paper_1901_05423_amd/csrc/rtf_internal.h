@@ -183,7 +183,7 @@ __device__ inline int64_t xcd_block() {
 
 hipError_t launch_build(const BuildArgs &a, hipStream_t st);
 hipError_t launch_sample(const Node *nodes, const Cell *cells, const Dist *dists,
-                         const int64_t *sample_off, int32_t D, int64_t n_total,
+                         const int64_t *sample_off, int32_t D, int64_t n_total, int64_t m_total,
                          const uint64_t *u, int64_t S, int32_t *idx, double *x,
                          hipStream_t st);
 hipError_t launch_sample_2d(const Node *nodes, const Cell *cells, const Dist *dists,

@@ -9,12 +9,13 @@ namespace rtf {
 namespace {
 
 // Index d with off[d] <= i < off[d+1] over off[0..D], found by a whole block
-// of 256 threads (uniform i): each round probes 256 evenly spaced offsets, so
+// of NT threads (uniform i): each round probes NT evenly spaced offsets, so
 // 10^4 distributions take two dependent loads.  Every thread must call it.
+template <int NT = 256>
 __device__ inline int32_t block_find_segment(const int64_t *off, int32_t D, int64_t i) {
     int32_t lo = 0, hi = D;  // off[lo] <= i < off[hi]
     while (hi - lo > 1) {
-        const int32_t step = (hi - lo + 255) / 256;
+        const int32_t step = (hi - lo + NT - 1) / NT;
         const int32_t p = lo + ((int32_t)threadIdx.x + 1) * step;
         const int below = (p < hi && off[p] <= i) ? 1 : 0;
         const int32_t nlo = lo + __syncthreads_count(below) * step;
@@ -230,6 +231,77 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
     }
 }
 
+// Batched sampling with the guide cells staged in LDS, for batches with
+// several samples per cell and distributions of at most LCELLS cells: a block
+// of SB_T threads takes a contiguous share of the samples, walks it one
+// distribution segment at a time, and copies a segment's cells into LDS when
+// the segment has at least STAGE_MIN samples per cell, so that a sample reads
+// its cell record from LDS and only the rare descents reach L2.  Copying a
+// record costs 64 streamed bytes; a random L2 read per sample costs more.
+constexpr int SB_T = 1024;
+constexpr int LCELLS = 1024;    // 64 KB of records: two blocks per CU
+constexpr int STAGE_MIN = 2;
+template <bool WANT_X>
+__global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void k_sample_staged(
+    const Node *__restrict__ nodes, const Cell *__restrict__ cells, const Dist *__restrict__ dists,
+    const int64_t *__restrict__ sample_off, int32_t D, int64_t n_total, const uint64_t *__restrict__ u,
+    int64_t S, int32_t *__restrict__ idx, double *__restrict__ x) {
+    __shared__ uint4 s_cell[LCELLS * 4];
+    const int64_t per = (S + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = xcd_block() * per;
+    const int64_t r1 = r0 + per < S ? r0 + per : S;
+    auto store = [&](int64_t s, const Dist &P, const Hit &h, uint64_t us) {
+        if (h.i < 0) {
+            idx[s] = -1;
+            if (WANT_X) x[s] = __builtin_nan("");
+            return;
+        }
+        __builtin_nontemporal_store((int32_t)(h.i - P.eo), idx + s);
+        if (WANT_X) __builtin_nontemporal_store(position(P, h, us), x + s);
+    };
+    for (int64_t s0 = r0; s0 < r1;) {  // uniform loop over the share's segments
+        const int32_t d = __builtin_amdgcn_readfirstlane(block_find_segment<SB_T>(sample_off, D, s0));
+        const int64_t de = sample_off[d + 1];
+        const int64_t e = de < r1 ? de : r1;
+        const Dist P = dists[d];
+        const bool zero = P.flags & DIST_ZERO;
+        const bool staged = !zero && P.m <= LCELLS && e - s0 >= STAGE_MIN * P.m;
+        if (staged) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(cells + P.co);
+            for (int64_t k = threadIdx.x; k < 4 * P.m; k += SB_T) s_cell[k] = src[k];
+            __syncthreads();
+        }
+        if (staged) {
+            // cells from LDS: two samples per step, both uniforms loaded
+            // together (the second index clamped: no branch)
+            const Cell *sc = reinterpret_cast<const Cell *>(s_cell);
+            for (int64_t sa = s0 + threadIdx.x; sa < e; sa += 2 * SB_T) {
+                const int64_t sb = sa + SB_T;
+                const uint64_t ua = __builtin_nontemporal_load(u + sa);
+                const uint64_t ub = __builtin_nontemporal_load(u + (sb < e ? sb : sa));
+                const Cell ca = load_cell(sc, (int64_t)mulhi64(ua, (uint64_t)P.m));
+                const Cell cb = load_cell(sc, (int64_t)mulhi64(ub, (uint64_t)P.m));
+                const Hit ha = resolve(nodes, ca, P, ua, n_total);
+                const Hit hb = resolve(nodes, cb, P, ub, n_total);
+                store(sa, P, ha, ua);
+                if (sb < e) store(sb, P, hb, ub);
+            }
+        } else {
+            // cells from global memory (segments too short to stage, or
+            // distributions with more than LCELLS cells)
+            for (int64_t sa = s0 + threadIdx.x; sa < e; sa += SB_T) {
+                const uint64_t us = __builtin_nontemporal_load(u + sa);
+                Hit h;
+                h.i = -1;
+                if (!zero) h = descend(nodes, cells, P, us, n_total);
+                store(sa, P, h, us);
+            }
+        }
+        if (staged) __syncthreads();  // before the next segment overwrites the cells
+        s0 = e;
+    }
+}
+
 template <bool WANT_X>
 __global__ __launch_bounds__(256) void k_sample_2d(const Node *__restrict__ nodes,
                                                    const Cell *__restrict__ cells,
@@ -363,10 +435,23 @@ inline int grid_for(int64_t S) {
 }  // namespace
 
 hipError_t launch_sample(const Node *nodes, const Cell *cells, const Dist *dists,
-                         const int64_t *sample_off, int32_t D, int64_t n_total,
+                         const int64_t *sample_off, int32_t D, int64_t n_total, int64_t m_total,
                          const uint64_t *u, int64_t S, int32_t *idx, double *x,
                          hipStream_t st) {
     const bool batched = sample_off != nullptr;
+    // many samples per cell and small distributions: stage the cells in LDS
+    // (two blocks of SB_T threads per CU)
+    if (batched && S >= (int64_t)STAGE_MIN * m_total && m_total <= (int64_t)LCELLS * D) {
+        int64_t nb = (S + 4 * SB_T - 1) / (4 * SB_T);
+        nb = nb < 512 ? nb : 512;
+        if (x)
+            hipLaunchKernelGGL((k_sample_staged<true>), dim3((unsigned)nb), dim3(SB_T), 0, st, nodes, cells, dists,
+                               sample_off, D, n_total, u, S, idx, x);
+        else
+            hipLaunchKernelGGL((k_sample_staged<false>), dim3((unsigned)nb), dim3(SB_T), 0, st, nodes, cells,
+                               dists, sample_off, D, n_total, u, S, idx, x);
+        return hipGetLastError();
+    }
     const dim3 g(batched ? grid_for((S + SCHUNK / 256 - 1) / (SCHUNK / 256)) : grid_for(S)), b(256);
     if (batched && x)
         hipLaunchKernelGGL((k_sample<true, true>), g, b, 0, st, nodes, cells, dists, sample_off,

@@ -93,6 +93,34 @@ def test_batched_zero_distribution(rtf, orc):
         assert np.array_equal(idx[10 * d:10 * d + 10], i_ref)
 
 
+def test_batched_staged_cells(rtf, orc):
+    """Batches with several samples per cell run the kernel that stages a
+    distribution's cells in LDS: distributions of at most 1024 cells staged,
+    one of 2000 cells read from global memory, a tiny one, a zero one."""
+    note("batched staged cells")
+    rng = np.random.default_rng(24)
+    ws = [random_weights(rng, 3000, zero_frac=0.2), random_weights(rng, 5000, skew=True),
+          random_weights(rng, 100), random_weights(rng, 4096)]
+    ws[3][-50:] = 0
+    check_batched(rtf, orc, ws, [700, 2000, 1, 1024], [300000, 200000, 5, 400003], 3)
+    # with a distribution of zero total weight among them
+    import paper_1901_05423_amd as rtfm
+    ws = [ws[0], np.zeros(50, np.uint32), ws[3]]
+    w = np.concatenate(ws)
+    eo, co = offsets([3000, 50, 4096]), offsets([700, 16, 1024])
+    f = rtf.build_batched(to_dev(w), to_dev(eo), to_dev(co))
+    with pytest.raises(rtfm.RtfError):
+        f.check()
+    so = offsets([100000, 20000, 100000])
+    u = rng.integers(0, 2 ** 64, int(so[-1]), dtype=np.uint64)
+    idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
+    idx, x = idx.cpu().numpy(), x.cpu().numpy()
+    assert (idx[so[1]:so[2]] == -1).all() and np.isnan(x[so[1]:so[2]]).all()
+    for d in (0, 2):
+        i_ref, x_ref = orc.search(ws[d], u[so[d]:so[d + 1]])
+        assert_samples(idx[so[d]:so[d + 1]], x[so[d]:so[d + 1]], i_ref, x_ref)
+
+
 def test_c4_batched_uneven_full(rtf, orc):
     """10,000 distributions, sizes log-uniform in [16, 65536], uniform or
     Pareto(1.2) weights, ceil(64 n_d / 1000) uniforms each."""
@@ -194,7 +222,7 @@ def test_c3_2d_full_map(rtf, orc):
     assert_forest(f, orc.forest(q_ref, elem_off=eo, cell_off=eo), "C3")
 
 
-def check_grad(rtf, orc, D, n, per, check_dists, seed):
+def check_grad(rtf, orc, D, n, per, check_dists, seed, ratio=1.0):
     import torch
     import paper_1901_05423_amd as rtfm
     from paper_1901_05423_amd import workloads as wl
@@ -206,7 +234,7 @@ def check_grad(rtf, orc, D, n, per, check_dists, seed):
     eo = to_dev(np.arange(D + 1, dtype=np.int64) * n)
     so = to_dev(np.arange(D + 1, dtype=np.int64) * per)
     u = to_dev(u_h)
-    x = rtfm.RTFSample.apply(v, u, eo, so, 1.0)
+    x = rtfm.RTFSample.apply(v, u, eo, so, ratio)
     L = torch.sin(7.0 * x).sum()
     L.backward()
     gz = z.grad.detach().double().cpu().numpy()
@@ -316,6 +344,7 @@ def test_grad_block_paths(rtf, orc):
 
 def test_c5_grad_full(rtf, orc):
     """256 distributions of 4096 softplus(N(0,1)) weights, 2^20 uniforms each,
+    1024 guide cells each (the sampling kernel stages them in LDS),
     L = sum sin(7x): dL/dlogits of 4 distributions checked against the oracle."""
     note("C5 grad D=256 n=4096 2^20 each")
-    check_grad(rtf, orc, 256, 4096, 1 << 20, [0, 1, 128, 255], 5)
+    check_grad(rtf, orc, 256, 4096, 1 << 20, [0, 1, 128, 255], 5, ratio=0.25)
