@@ -302,71 +302,68 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
     }
 }
 
+// The 2D inversion of Sec. 5, component by component: the row from the
+// marginal (distribution 0), then the column from that row's distribution.
+// The marginal's guide cells are staged in LDS when it has at most LCELLS
+// cells, so a pair resolves its row without a global record read.  A pair is
+// read with one 16-byte load and written with one 8-byte and one 16-byte
+// store, so every wave access covers whole consecutive lines.  Blocks of SB_T
+// threads, two per CU, one pair per lane and step.
 template <bool WANT_X>
-__global__ __launch_bounds__(256) void k_sample_2d(const Node *__restrict__ nodes,
-                                                   const Cell *__restrict__ cells,
-                                                   const Dist *__restrict__ dists, int32_t D,
-                                                   int64_t n_total,
-                                                   const uint64_t *__restrict__ u2, int64_t S,
-                                                   int32_t *__restrict__ rc,
-                                                   double *__restrict__ xy) {
+__global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void k_sample_2d_staged(
+    const Node *__restrict__ nodes, const Cell *__restrict__ cells, const Dist *__restrict__ dists, int32_t D,
+    int64_t n_total, const uint64_t *__restrict__ u2, int64_t S, int32_t *__restrict__ rc,
+    double *__restrict__ xy) {
     typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
     typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
     typedef double f64x2 __attribute__((ext_vector_type(2)));
-    // a pair is read with one 16-byte load and written with one 8-byte and one
-    // 16-byte store, so every wave access covers whole consecutive lines; a
-    // lane takes two pairs at a time (s and s + T) and issues the loads of
-    // each step of both chains (row record, row parameters, column record)
-    // together, two dependent chains in flight instead of one
+    __shared__ uint4 s_cell[LCELLS * 4];
     const u64x2 *up = reinterpret_cast<const u64x2 *>(u2);
     i32x2 *rcp = reinterpret_cast<i32x2 *>(rc);
     f64x2 *xyp = reinterpret_cast<f64x2 *>(xy);
     const int64_t T = (int64_t)gridDim.x * blockDim.x;
-    const Dist &M = dists[0];
+    const Dist M = dists[0];
     const bool mzero = (M.flags & DIST_ZERO) != 0;
-    for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s0 < S; s0 += 2 * T) {
-        int64_t s[2] = {s0, s0 + T};
-        bool ok[2] = {true, s0 + T < S};
-        u64x2 uu[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) uu[k] = ok[k] ? __builtin_nontemporal_load(up + s[k]) : u64x2{0, 0};
-        Cell cr[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) cr[k] = load_cell(cells, cell_index(M, uu[k].x));
-        Hit hr[2];
-        int64_t r[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            hr[k].i = -1;
-            if (!mzero) hr[k] = resolve(nodes, cr[k], M, uu[k].x, n_total);
-            r[k] = hr[k].i - M.eo;
-            // the marginal must have one weight per row distribution 1..D-1
-            if (hr[k].i < 0 || 1 + r[k] >= D) r[k] = -1;
-        }
-        Dist R[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) R[k] = dists[r[k] >= 0 ? 1 + r[k] : 0];
-        Cell cc[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k) cc[k] = load_cell(cells, cell_index(R[k], uu[k].y));
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            if (!ok[k]) continue;
-            i32x2 out = {-1, -1};
-            f64x2 pos = {__builtin_nan(""), __builtin_nan("")};
-            if (r[k] >= 0) {
-                out.x = (int32_t)r[k];
-                if (WANT_X) pos.x = position(M, hr[k], uu[k].x);
-                Hit hc;
-                hc.i = -1;
-                if (!(R[k].flags & DIST_ZERO)) hc = resolve(nodes, cc[k], R[k], uu[k].y, n_total);
-                if (hc.i >= 0) {
-                    out.y = (int32_t)(hc.i - R[k].eo);
-                    if (WANT_X) pos.y = position(R[k], hc, uu[k].y);
-                }
+    const bool staged = !mzero && M.m <= LCELLS;
+    if (staged) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(cells + M.co);
+        for (int64_t k = threadIdx.x; k < 4 * M.m; k += SB_T) s_cell[k] = src[k];
+        __syncthreads();
+    }
+    auto pair = [&](int64_t s, const u64x2 uu, const Cell &cr) {
+        i32x2 out = {-1, -1};
+        f64x2 pos = {__builtin_nan(""), __builtin_nan("")};
+        Hit hr;
+        hr.i = -1;
+        if (!mzero) hr = resolve(nodes, cr, M, uu.x, n_total);
+        const int64_t r = hr.i - M.eo;
+        // the marginal must have one weight per row distribution 1..D-1
+        if (hr.i >= 0 && 1 + r < D) {
+            out.x = (int32_t)r;
+            if (WANT_X) pos.x = position(M, hr, uu.x);
+            const Dist R = dists[1 + r];
+            Hit hc;
+            hc.i = -1;
+            if (!(R.flags & DIST_ZERO)) hc = descend(nodes, cells, R, uu.y, n_total);
+            if (hc.i >= 0) {
+                out.y = (int32_t)(hc.i - R.eo);
+                if (WANT_X) pos.y = position(R, hc, uu.y);
             }
-            __builtin_nontemporal_store(out, rcp + s[k]);
-            if (WANT_X) __builtin_nontemporal_store(pos, xyp + s[k]);
+        }
+        __builtin_nontemporal_store(out, rcp + s);
+        if (WANT_X) __builtin_nontemporal_store(pos, xyp + s);
+    };
+    const int64_t s_first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (staged) {
+        const Cell *sc = reinterpret_cast<const Cell *>(s_cell);
+        for (int64_t s = s_first; s < S; s += T) {
+            const u64x2 uu = __builtin_nontemporal_load(up + s);
+            pair(s, uu, load_cell(sc, (int64_t)mulhi64(uu.x, (uint64_t)M.m)));
+        }
+    } else {
+        for (int64_t s = s_first; s < S; s += T) {
+            const u64x2 uu = __builtin_nontemporal_load(up + s);
+            pair(s, uu, load_cell(cells, mzero ? 0 : cell_index(M, uu.x)));
         }
     }
 }
@@ -471,12 +468,15 @@ hipError_t launch_sample(const Node *nodes, const Cell *cells, const Dist *dists
 hipError_t launch_sample_2d(const Node *nodes, const Cell *cells, const Dist *dists,
                             int32_t D, int64_t n_total, const uint64_t *u2, int64_t S,
                             int32_t *rc, double *xy, hipStream_t st) {
-    const dim3 g(grid_for(S)), b(256);
+    // two blocks per CU, each copying the marginal's records once
+    int64_t nb = (S + SB_T - 1) / SB_T;
+    nb = nb < 512 ? nb : 512;
+    const dim3 g((unsigned)nb), b(SB_T);
     if (xy)
-        hipLaunchKernelGGL((k_sample_2d<true>), g, b, 0, st, nodes, cells, dists, D, n_total, u2,
+        hipLaunchKernelGGL((k_sample_2d_staged<true>), g, b, 0, st, nodes, cells, dists, D, n_total, u2,
                            S, rc, xy);
     else
-        hipLaunchKernelGGL((k_sample_2d<false>), g, b, 0, st, nodes, cells, dists, D, n_total,
+        hipLaunchKernelGGL((k_sample_2d_staged<false>), g, b, 0, st, nodes, cells, dists, D, n_total,
                            u2, S, rc, xy);
     return hipGetLastError();
 }
