@@ -102,7 +102,7 @@ def sample_bytes_model(key, child, table, K, aux, m, u):
     g = ((u.astype(object) * m) >> 64).astype(np.int64)
     ref = table[g].astype(np.int64)
     ax = aux[g].astype(np.int64)
-    deeper = (ref >= 0) & (ax >= 0) & (u >= K[g, 6])
+    deeper = (ref >= 0) & (ax >= 0) & (u >= K[g, K.shape[1] - 1])
     j = np.where(deeper, ax, -1).astype(np.int64)
     visits = np.zeros(u.size, np.int64)
     active = j >= 0
@@ -140,7 +140,7 @@ def loads_forest_records(key, child, table, K, aux, m, u):
     g = ((u.astype(object) * m) >> 64).astype(np.int64)
     ref = table[g].astype(np.int64)
     ax = aux[g].astype(np.int64)
-    deeper = (ref >= 0) & (ax >= 0) & (u >= K[g, 6])
+    deeper = (ref >= 0) & (ax >= 0) & (u >= K[g, K.shape[1] - 1])
     j = np.where(deeper, ax, -1).astype(np.int64)
     visits = np.zeros(u.size, np.int64)
     active = j >= 0
@@ -583,8 +583,9 @@ def run_c5(args):
     so = torch.arange(D + 1, dtype=torch.int64, device=dev) * per
     v = torch.nn.functional.softplus(z).reshape(-1).contiguous()
     from paper_1901_05423_amd.plan import BatchedPlan
-    co = torch.arange(D + 1, dtype=torch.int64, device=dev) * (nd // 4)
-    plan = BatchedPlan(eo, co, so, D * nd, D * (nd // 4), D * per)
+    md = max(1, int(round(nd * batch_ratio(args))))
+    co = torch.arange(D + 1, dtype=torch.int64, device=dev) * md
+    plan = BatchedPlan(eo, co, so, D * nd, D * md, D * per)
     plan.run(v, u)
     plan.check()
     f = plan
@@ -600,7 +601,7 @@ def run_c5(args):
     t_bwd = event_time(bwd, args.steps)
     S = D * per
     res = common(METRIC, "samples/s", S / ((t_fwd + t_bwd) * 1e-3), t_fwd + t_bwd, args, "u64",
-                 "C5: 256 distributions x 4096 softplus(N(0,1)) weights, m_d=0.25n_d, 2^20 uniforms each; "
+                 f"C5: 256 distributions x 4096 softplus(N(0,1)) weights, m_d={md}, 2^20 uniforms each; "
                  "forward quantise + build + sample with x, backward dL/dw of L = sum sin(7x)",
                  ms_forward=t_fwd, ms_backward=t_bwd,
                  forward_samples_s=S / (t_fwd * 1e-3), backward_samples_s=S / (t_bwd * 1e-3))

@@ -28,6 +28,7 @@ RTF_ERR_VALUE = 6
 
 NODE_BYTES = 16
 CELL_BYTES = 64
+CELL_KEYS = 7  # keys per cell record; the last int64 word holds (ref, aux)
 
 
 class RtfError(RuntimeError):
@@ -160,11 +161,11 @@ class Forest:
 
     def cell_view(self):
         """Device view of the guide cell records: int64 [m_total, 8] holding
-        the seven keys k[0..6] and the (ref, aux) int32 pair."""
+        the keys k[0..6] and the (ref, aux) int32 pair."""
         torch = _torch()
         off = self.desc.cells - self.ws.data_ptr()
         return self.ws[off:off + CELL_BYTES * self.m_total].view(torch.int64).view(
-            self.m_total, 8)
+            self.m_total, CELL_KEYS + 1)
 
     def export(self, stream=None, with_cells=False):
         """Host copies: key uint64[n], child int32[n, 2], table int32[m] (the guide
@@ -173,17 +174,17 @@ class Forest:
         import numpy as np
         n, m = self.n_total, self.m_total
         raw = np.zeros((n, 2), np.uint64)
-        cells = np.zeros((m, 8), np.uint64)
+        cells = np.zeros((m, CELL_KEYS + 1), np.uint64)
         W = np.zeros(self.D, np.uint64)
         p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         _check(lib().rtf_forest_export(ctypes.byref(self.desc), p(raw), p(cells), p(W),
                                        _stream(stream)), "rtf_forest_export")
         key = np.ascontiguousarray(raw[:, 0])
         child = np.ascontiguousarray(raw[:, 1]).view(np.int32).reshape(n, 2)
-        refs = np.ascontiguousarray(cells[:, 7]).view(np.int32).reshape(m, 2)
+        refs = np.ascontiguousarray(cells[:, CELL_KEYS]).view(np.int32).reshape(m, 2)
         table = np.ascontiguousarray(refs[:, 0])
         if with_cells:
-            return key, child, table, W, (np.ascontiguousarray(cells[:, :7]),
+            return key, child, table, W, (np.ascontiguousarray(cells[:, :CELL_KEYS]),
                                           np.ascontiguousarray(refs[:, 1]))
         return key, child, table, W
 

@@ -181,19 +181,23 @@ __device__ inline Leaf make_leaf(uint64_t C, const Dist &P) {
     return L;
 }
 
-// A 64-byte cell record with four 16-byte stores.
+// A cell record with CELL_WORDS 16-byte stores.
 __device__ inline void store_cell(Cell *cells, int64_t g, const uint64_t *k, int32_t ref,
                                   int32_t aux) {
     uint4 *p = reinterpret_cast<uint4 *>(cells + g);
-    p[0] = make_uint4((uint32_t)k[0], (uint32_t)(k[0] >> 32), (uint32_t)k[1], (uint32_t)(k[1] >> 32));
-    p[1] = make_uint4((uint32_t)k[2], (uint32_t)(k[2] >> 32), (uint32_t)k[3], (uint32_t)(k[3] >> 32));
-    p[2] = make_uint4((uint32_t)k[4], (uint32_t)(k[4] >> 32), (uint32_t)k[5], (uint32_t)(k[5] >> 32));
-    p[3] = make_uint4((uint32_t)k[6], (uint32_t)(k[6] >> 32), (uint32_t)ref, (uint32_t)aux);
+#pragma unroll
+    for (int w = 0; w + 1 < CELL_WORDS; ++w)
+        p[w] = make_uint4((uint32_t)k[2 * w], (uint32_t)(k[2 * w] >> 32), (uint32_t)k[2 * w + 1],
+                          (uint32_t)(k[2 * w + 1] >> 32));
+    p[CELL_WORDS - 1] = make_uint4((uint32_t)k[CELL_KEYS - 1], (uint32_t)(k[CELL_KEYS - 1] >> 32), (uint32_t)ref,
+                                   (uint32_t)aux);
 }
 
 // The record of a cell covered by interval i alone, whose keys are lo and hi.
 __device__ inline void store_covered(Cell *cells, int64_t g, uint64_t lo, uint64_t hi, int32_t i) {
-    const uint64_t k[7] = {lo, hi, 0, 0, 0, 0, 0};
+    uint64_t k[CELL_KEYS];
+#pragma unroll
+    for (int t = 0; t < CELL_KEYS; ++t) k[t] = t == 0 ? lo : (t == 1 ? hi : 0);
     store_cell(cells, g, k, ~i, ~i);
 }
 
@@ -203,7 +207,7 @@ __device__ inline void store_covered(Cell *cells, int64_t g, uint64_t lo, uint64
 // more than CELL_BOUNDS lower bounds).
 __device__ inline void root_record(Cell *cells, int64_t g, int32_t a, uint64_t kprev,
                                    const uint64_t *key, const int32_t *cell, int32_t c1) {
-    uint64_t k[7];
+    uint64_t k[CELL_KEYS];
     k[0] = key[0] == 0 ? 0 : kprev;  // 0 at a distribution start
     k[1] = key[0];
     int cnt = 1;  // lower bounds of the cell among a .. a+t-1
@@ -1132,19 +1136,21 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
     // the last run whose offset is at most p (runs[0].off = 0)
     int64_t r = wave_run([&](int64_t d) { return (int64_t)a.runs[d].off <= p; }, nrun - 1);
     // the records as a flat array of 16-byte words, so that one store of the
-    // wave writes 1 KiB in a row: lane l always writes word l % 4 of a record
-    // (keys k0 and k1, zeros, zeros, then zero, ref and aux)
+    // wave writes 1 KiB in a row: lane l always writes word l % CELL_WORDS of
+    // a record (keys k0 and k1, zeros, then zero, ref and aux in the last)
+    static_assert(64 % CELL_WORDS == 0, "a wave store covers whole records");
     uint4 *words = reinterpret_cast<uint4 *>(a.cells);
+    const int wq = lane % CELL_WORDS;
     while (p < p_end) {
         const Run R = a.runs[r];
         const int64_t e = (int64_t)R.off + R.len < p_end ? (int64_t)R.off + R.len : p_end;
         const uint32_t ni = ~(uint32_t)R.i;
-        const uint4 v = (lane & 3) == 0   ? make_uint4((uint32_t)R.k0, (uint32_t)(R.k0 >> 32), (uint32_t)R.k1,
-                                                       (uint32_t)(R.k1 >> 32))
-                        : (lane & 3) == 3 ? make_uint4(0u, 0u, ni, ni)
-                                          : make_uint4(0u, 0u, 0u, 0u);
-        const int64_t w1 = 4 * ((int64_t)R.lo + (e - (int64_t)R.off));
-        for (int64_t w = 4 * ((int64_t)R.lo + (p - (int64_t)R.off)) + lane; w < w1; w += 64) words[w] = v;
+        const uint4 v = wq == 0                ? make_uint4((uint32_t)R.k0, (uint32_t)(R.k0 >> 32), (uint32_t)R.k1,
+                                                            (uint32_t)(R.k1 >> 32))
+                        : wq == CELL_WORDS - 1 ? make_uint4(0u, 0u, ni, ni)
+                                               : make_uint4(0u, 0u, 0u, 0u);
+        const int64_t w1 = CELL_WORDS * ((int64_t)R.lo + (e - (int64_t)R.off));
+        for (int64_t w = CELL_WORDS * ((int64_t)R.lo + (p - (int64_t)R.off)) + lane; w < w1; w += 64) words[w] = v;
         p = e;
         ++r;
     }

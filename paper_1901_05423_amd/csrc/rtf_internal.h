@@ -40,25 +40,31 @@ struct alignas(16) Node {
 // Guide-table cell record, 64 bytes: one memory access per sample in the
 // common case.  `ref` is the paper's guide entry (Sec. 2.5, 3.2): the cell's
 // first node a, or ~i when one interval i covers the whole cell.  Beside it
-// the record keeps the keys that finish a sample without the tree:
+// the record keeps the keys that finish a sample without the tree
+// (K = CELL_KEYS - 1 = CELL_BOUNDS + 1):
 //   ref = ~i < 0:  k[0] = U_i, k[1] = U_{i+1} (KEY_END at the distribution's
 //                  end), aux = ref.
 //   ref = a >= 0:  the cell holds the c lower bounds U_a .. U_{a+c-1};
 //                  k[0] = U_{a-1} (0 at a distribution start) and
-//                  k[t] = U_{a+t-1} for t = 1 .. min(c + 1, 6), where
+//                  k[t] = U_{a+t-1} for t = 1 .. min(c + 1, K), where
 //                  U_{a+c} (KEY_END at the distribution's end) is the upper
 //                  end of the cell's last interval.
 //                  c <= CELL_BOUNDS: aux = ~c, and the record resolves every
 //                  sample of the cell.
 //                  c > CELL_BOUNDS: aux = child 1 of node a, the root of the
-//                  cell's tree; the record resolves u < k[6], larger u
+//                  cell's tree; the record resolves u < k[K], larger u
 //                  descend the tree from aux.
-// Key slots a record does not use hold 0.
+// Key slots a record does not use hold 0.  (A 128-byte record with 13 bounds
+// at half the cells was measured too: fewer descents, no faster sampling,
+// and twice the registers per record in the kernels that hold two.)
 constexpr int CELL_BOUNDS = 5;
+constexpr int CELL_KEYS = CELL_BOUNDS + 2;
 struct alignas(64) Cell {
-    uint64_t k[7];
+    uint64_t k[CELL_KEYS];
     int32_t ref, aux;
 };
+static_assert(sizeof(Cell) == 64, "cell records are 64 bytes");
+constexpr int CELL_WORDS = sizeof(Cell) / 16;  // 16-byte words of a record
 constexpr uint64_t KEY_END = ~0ull;
 
 // A listed guide-table run: cells [lo, lo + len) are all covered by interval

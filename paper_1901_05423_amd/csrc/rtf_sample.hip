@@ -38,17 +38,17 @@ __device__ inline Node load_node(const Node *nodes, int64_t j) {
 
 __device__ inline Cell load_cell(const Cell *cells, int64_t g) {
     const uint4 *p = reinterpret_cast<const uint4 *>(cells + g);
-    const uint4 a = p[0], b = p[1], c = p[2], d = p[3];
+    uint4 v[CELL_WORDS];
+#pragma unroll
+    for (int w = 0; w < CELL_WORDS; ++w) v[w] = p[w];  // all in flight together
     Cell r;
-    r.k[0] = ((uint64_t)a.y << 32) | a.x;
-    r.k[1] = ((uint64_t)a.w << 32) | a.z;
-    r.k[2] = ((uint64_t)b.y << 32) | b.x;
-    r.k[3] = ((uint64_t)b.w << 32) | b.z;
-    r.k[4] = ((uint64_t)c.y << 32) | c.x;
-    r.k[5] = ((uint64_t)c.w << 32) | c.z;
-    r.k[6] = ((uint64_t)d.y << 32) | d.x;
-    r.ref = (int32_t)d.z;
-    r.aux = (int32_t)d.w;
+#pragma unroll
+    for (int w = 0; w < CELL_WORDS; ++w) {
+        r.k[2 * w] = ((uint64_t)v[w].y << 32) | v[w].x;
+        if (w + 1 < CELL_WORDS) r.k[2 * w + 1] = ((uint64_t)v[w].w << 32) | v[w].z;
+    }
+    r.ref = (int32_t)v[CELL_WORDS - 1].z;
+    r.aux = (int32_t)v[CELL_WORDS - 1].w;
     return r;
 }
 
@@ -86,7 +86,7 @@ __device__ inline Hit resolve(const Node *nodes, const Cell &c, const Dist &P, u
         h.i = ~(int64_t)c.ref;
         h.lo = c.k[0];
         h.hi = c.k[1];
-    } else if (c.aux < 0 || u < c.k[6]) {
+    } else if (c.aux < 0 || u < c.k[CELL_KEYS - 1]) {
         const int lim = c.aux < 0 ? ~c.aux : CELL_BOUNDS;  // lower bounds held
         int j = 0;
         uint64_t lo = c.k[0], hi = c.k[1];
@@ -237,7 +237,8 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
 // distribution segment at a time, and copies a segment's cells into LDS when
 // the segment has at least STAGE_MIN samples per cell, so that a sample reads
 // its cell record from LDS and only the rare descents reach L2.  Copying a
-// record costs 64 streamed bytes; a random L2 read per sample costs more.
+// record streams 64 bytes, at most 32 per sample of the segment; a random L2
+// read per sample costs more.
 constexpr int SB_T = 1024;
 constexpr int LCELLS = 1024;    // 64 KB of records: two blocks per CU
 constexpr int STAGE_MIN = 2;
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
     const Node *__restrict__ nodes, const Cell *__restrict__ cells, const Dist *__restrict__ dists,
     const int64_t *__restrict__ sample_off, int32_t D, int64_t n_total, const uint64_t *__restrict__ u,
     int64_t S, int32_t *__restrict__ idx, double *__restrict__ x) {
-    __shared__ uint4 s_cell[LCELLS * 4];
+    __shared__ uint4 s_cell[LCELLS * CELL_WORDS];
     const int64_t per = (S + gridDim.x - 1) / gridDim.x;
     const int64_t r0 = xcd_block() * per;
     const int64_t r1 = r0 + per < S ? r0 + per : S;
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
         const bool staged = !zero && P.m <= LCELLS && e - s0 >= STAGE_MIN * P.m;
         if (staged) {
             const uint4 *src = reinterpret_cast<const uint4 *>(cells + P.co);
-            for (int64_t k = threadIdx.x; k < 4 * P.m; k += SB_T) s_cell[k] = src[k];
+            for (int64_t k = threadIdx.x; k < CELL_WORDS * P.m; k += SB_T) s_cell[k] = src[k];
             __syncthreads();
         }
         if (staged) {
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
     typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
     typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
     typedef double f64x2 __attribute__((ext_vector_type(2)));
-    __shared__ uint4 s_cell[LCELLS * 4];
+    __shared__ uint4 s_cell[LCELLS * CELL_WORDS];
     const u64x2 *up = reinterpret_cast<const u64x2 *>(u2);
     i32x2 *rcp = reinterpret_cast<i32x2 *>(rc);
     f64x2 *xyp = reinterpret_cast<f64x2 *>(xy);
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
     const bool staged = !mzero && M.m <= LCELLS;
     if (staged) {
         const uint4 *src = reinterpret_cast<const uint4 *>(cells + M.co);
-        for (int64_t k = threadIdx.x; k < 4 * M.m; k += SB_T) s_cell[k] = src[k];
+        for (int64_t k = threadIdx.x; k < CELL_WORDS * M.m; k += SB_T) s_cell[k] = src[k];
         __syncthreads();
     }
     auto pair = [&](int64_t s, const u64x2 uu, const Cell &cr) {

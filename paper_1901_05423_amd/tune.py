@@ -17,7 +17,7 @@ import json
 import math
 import os
 
-CANDIDATES = (0.25, 0.5, 1.0, 2.0)
+CANDIDATES = (0.125, 0.25, 0.5, 1.0, 2.0)
 
 
 def cache_path() -> str:

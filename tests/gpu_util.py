@@ -65,6 +65,7 @@ def assert_samples(idx_gpu, x_gpu, idx_ref, x_ref):
 
 
 CELL_BOUNDS = 5  # lower bounds a guide cell record holds
+CELL_KEYS = CELL_BOUNDS + 2  # keys of a record: k[0] .. k[CELL_BOUNDS + 1]
 
 
 def _cells_of(key, x, eo, co):
@@ -87,7 +88,7 @@ def expected_cells(ref):
     a = np.where(node, table, ~table)  # first node a, or covering leaf i
     end = eo[np.searchsorted(eo, a, side="right")]  # end of a's distribution
     g = np.arange(m, dtype=np.int64)
-    K = np.zeros((m, 7), np.uint64)
+    K = np.zeros((m, CELL_KEYS), np.uint64)
     prev = np.where(key[a] == 0, np.uint64(0), key[np.maximum(a - 1, 0)])
     nxt = np.where(a + 1 < end, key[np.minimum(a + 1, n - 1)], MAX)
     K[:, 0] = np.where(node, prev, key[a])

@@ -5,7 +5,7 @@ tree descent the record points to (Alg. 2 with the guide entry of Sec. 3.2)."""
 import numpy as np
 import pytest
 
-from gpu_util import CELL_BOUNDS, TWO64, critical_u, expected_cells, random_weights
+from gpu_util import CELL_BOUNDS, CELL_KEYS, TWO64, critical_u, expected_cells, random_weights
 
 
 def model_sample(ref, K, aux, u):
@@ -20,7 +20,7 @@ def model_sample(ref, K, aux, u):
             out[s] = ~t
             continue
         a = int(aux[g])
-        if a < 0 or us < int(K[g, 6]):
+        if a < 0 or us < int(K[g, CELL_KEYS - 1]):
             lim = ~a if a < 0 else CELL_BOUNDS
             j = sum(1 for q in range(1, lim + 1) if int(K[g, q]) <= us)
             out[s] = t - 1 + j
@@ -36,6 +36,7 @@ CASES = [
     # (n, m, zero_frac, skew): cells from nearly empty to hundreds of leaves
     (1000, 1000, 0.0, False),
     (5000, 1000, 0.0, False),   # about 5 leaves per cell: both record paths
+    (20000, 1000, 0.0, False),  # about 20 per cell: mostly descents
     (5000, 400, 0.1, False),    # dense cells: descents from aux
     (3000, 6000, 0.3, True),    # sparse, skewed, zero runs: covered cells
     (2048, 1, 0.0, False),      # one cell: a single tree
