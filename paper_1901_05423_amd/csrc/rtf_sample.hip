@@ -52,6 +52,16 @@ __device__ inline Cell load_cell(const Cell *cells, int64_t g) {
     return r;
 }
 
+// Marks every word of a record as used here, so that the record's loads,
+// issued before, complete together (one wait).  Without it, when x is not
+// wanted, the compiler splits the record load along the branches that use
+// each word: up to three round trips to the same line, one after another.
+__device__ inline void pin_cell(Cell &c) {
+#pragma unroll
+    for (int t = 0; t < CELL_KEYS; ++t) asm volatile("" : "+v"(c.k[t]));
+    asm volatile("" : "+v"(c.ref), "+v"(c.aux));
+}
+
 // A sampled leaf with the keys of its interval's two ends (KEY_END for the
 // distribution's end); leaf -1 flags a damaged workspace.
 struct Hit {
@@ -75,43 +85,43 @@ __device__ inline int64_t cell_index(const Dist &P, uint64_t u) {
 
 __device__ inline Hit descend(const Node *nodes, const Cell *cells, const Dist &P, uint64_t u,
                               int64_t n_total) {
-    return resolve(nodes, load_cell(cells, cell_index(P, u)), P, u, n_total);
+    Cell c = load_cell(cells, cell_index(P, u));
+    pin_cell(c);
+    return resolve(nodes, c, P, u, n_total);
 }
 
 // The sample's leaf from its cell record c (and, past the record, the tree).
+// The record's own answer is computed for every kind of cell with selects
+// only (a covered cell is a record holding no bounds); only a descent
+// branches.
 __device__ inline Hit resolve(const Node *nodes, const Cell &c, const Dist &P, uint64_t u,
                               int64_t n_total) {
-    Hit h;
-    if (c.ref < 0) {  // one interval covers the cell
-        h.i = ~(int64_t)c.ref;
-        h.lo = c.k[0];
-        h.hi = c.k[1];
-    } else if (c.aux < 0 || u < c.k[CELL_KEYS - 1]) {
-        const int lim = c.aux < 0 ? ~c.aux : CELL_BOUNDS;  // lower bounds held
-        int j = 0;
-        uint64_t lo = c.k[0], hi = c.k[1];
+    const bool covered = c.ref < 0;  // one interval covers the cell
+    const int lim = covered ? 0 : (c.aux < 0 ? ~c.aux : CELL_BOUNDS);  // lower bounds held
+    int j = 0;
+    uint64_t lo = c.k[0], hi = c.k[1];
 #pragma unroll
-        for (int t = 1; t <= CELL_BOUNDS; ++t) {
-            if (t <= lim && c.k[t] <= u) {
-                j = t;
-                lo = c.k[t];
-                hi = c.k[t + 1];
-            }
-        }
-        h.i = (int64_t)c.ref - 1 + j;
-        h.lo = lo;
-        h.hi = hi;
-    } else {
-        int32_t j = c.aux;
-        for (int64_t steps = 0; j >= 0; ++steps) {
-            if (j >= n_total || steps > n_total) {
+    for (int t = 1; t <= CELL_BOUNDS; ++t) {
+        const bool le = t <= lim && c.k[t] <= u;
+        j = le ? t : j;
+        lo = le ? c.k[t] : lo;
+        hi = le ? c.k[t + 1] : hi;
+    }
+    Hit h;
+    h.i = covered ? ~(int64_t)c.ref : (int64_t)c.ref - 1 + j;
+    h.lo = lo;
+    h.hi = hi;
+    if (!covered && c.aux >= 0 && u >= c.k[CELL_KEYS - 1]) {  // past the record: the tree
+        int32_t jn = c.aux;
+        for (int64_t steps = 0; jn >= 0; ++steps) {
+            if (jn >= n_total || steps > n_total) {
                 h.i = -1;
                 return h;
             }
-            const Node nd = load_node(nodes, j);
-            j = (u < nd.key) ? nd.c0 : nd.c1;
+            const Node nd = load_node(nodes, jn);
+            jn = (u < nd.key) ? nd.c0 : nd.c1;
         }
-        h.i = ~(int64_t)j;
+        h.i = ~(int64_t)jn;
         if (h.i < P.eo || h.i >= P.eo + P.n) {
             h.i = -1;
             return h;
@@ -193,8 +203,10 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
         const uint64_t ua = __builtin_nontemporal_load(u + sa);
         const uint64_t ub = __builtin_nontemporal_load(u + (has_b ? sb : sa));  // no branch
         const bool za = Pa.flags & DIST_ZERO, zb = Pb.flags & DIST_ZERO;
-        const Cell ca = load_cell(cells, za ? 0 : cell_index(Pa, ua));
-        const Cell cb = load_cell(cells, zb ? 0 : cell_index(Pb, ub));
+        Cell ca = load_cell(cells, za ? 0 : cell_index(Pa, ua));
+        Cell cb = load_cell(cells, zb ? 0 : cell_index(Pb, ub));
+        pin_cell(ca);
+        pin_cell(cb);
         Hit ha, hb;
         ha.i = hb.i = -1;
         if (!za) ha = resolve(nodes, ca, Pa, ua, n_total);
@@ -280,8 +292,10 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
                 const int64_t sb = sa + SB_T;
                 const uint64_t ua = __builtin_nontemporal_load(u + sa);
                 const uint64_t ub = __builtin_nontemporal_load(u + (sb < e ? sb : sa));
-                const Cell ca = load_cell(sc, (int64_t)mulhi64(ua, (uint64_t)P.m));
-                const Cell cb = load_cell(sc, (int64_t)mulhi64(ub, (uint64_t)P.m));
+                Cell ca = load_cell(sc, (int64_t)mulhi64(ua, (uint64_t)P.m));
+                Cell cb = load_cell(sc, (int64_t)mulhi64(ub, (uint64_t)P.m));
+                pin_cell(ca);
+                pin_cell(cb);
                 const Hit ha = resolve(nodes, ca, P, ua, n_total);
                 const Hit hb = resolve(nodes, cb, P, ub, n_total);
                 store(sa, P, ha, ua);
@@ -359,12 +373,16 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
         const Cell *sc = reinterpret_cast<const Cell *>(s_cell);
         for (int64_t s = s_first; s < S; s += T) {
             const u64x2 uu = __builtin_nontemporal_load(up + s);
-            pair(s, uu, load_cell(sc, (int64_t)mulhi64(uu.x, (uint64_t)M.m)));
+            Cell cr = load_cell(sc, (int64_t)mulhi64(uu.x, (uint64_t)M.m));
+            pin_cell(cr);
+            pair(s, uu, cr);
         }
     } else {
         for (int64_t s = s_first; s < S; s += T) {
             const u64x2 uu = __builtin_nontemporal_load(up + s);
-            pair(s, uu, load_cell(cells, mzero ? 0 : cell_index(M, uu.x)));
+            Cell cr = load_cell(cells, mzero ? 0 : cell_index(M, uu.x));
+            pin_cell(cr);
+            pair(s, uu, cr);
         }
     }
 }
