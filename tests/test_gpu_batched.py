@@ -34,6 +34,8 @@ def check_batched(rtf, orc, ws, cells, sample_counts, seed):
     u = rng.integers(0, 2 ** 64, int(so[-1]), dtype=np.uint64)
     idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
     idx, x = idx.cpu().numpy(), x.cpu().numpy()
+    idx_only, none = rtf.sample_batched(f, to_dev(so), to_dev(u), want_x=False)
+    assert none is None and np.array_equal(idx_only.cpu().numpy(), idx)
     for d, wd in enumerate(ws):
         a, b = so[d], so[d + 1]
         if a == b:
@@ -178,6 +180,8 @@ def check_2d(rtf, orc, img, marginal, pairs, seed, zero_rows=False):
     u2 = rng.integers(0, 2 ** 64, 2 * pairs, dtype=np.uint64)
     rc, xy = rtf.sample_2d(f, to_dev(u2))
     rc, xy = rc.cpu().numpy(), xy.cpu().numpy()
+    rc_only, none = rtf.sample_2d(f, to_dev(u2), want_xy=False)
+    assert none is None and np.array_equal(rc_only.cpu().numpy(), rc)
     r_ref, y_ref = orc.search(q_ref[:R], u2[0::2])
     assert_samples(rc[:, 0], xy[:, 0], r_ref, y_ref)
     c_ref = np.empty(pairs, np.int32)
