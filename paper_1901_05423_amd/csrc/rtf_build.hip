@@ -666,8 +666,10 @@ __device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
     }
 }
 
+// Three blocks per CU (the LDS allows three): the batched instance is held
+// to 80 registers for that, at the price of a few spilled ones.
 template <bool BATCHED>
-__global__ __launch_bounds__(BT) void k_build_tile(BuildArgs a, bool vec) {
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_build_tile(BuildArgs a, bool vec) {
     __shared__ TileSmem sm;
     const int tid = threadIdx.x;
     const int64_t t = blockIdx.x;
