@@ -11,14 +11,15 @@
 // scan over the levels held in LDS, and writes its own 16-byte record once.
 // With m proportional to n the cells hold a few leaves, so the scans are a few
 // LDS reads; scans that leave a tile's LDS window or exceed SCAN_CAP steps are
-// finished by a fix-up kernel that uses binary searches on the global keys.
+// finished by a fix-up kernel that searches the global keys.
 //
 // Kernels (stream order):
-//   k_offsets    copy offsets into the workspace, clear the status word
-//   k_tile_sums  per-tile weight sums (+ in-tile prefix at distribution starts)
+//   k_tile_sums    per-tile weight sums (+ in-tile prefix at distribution
+//                  starts); block 0 copies the offsets into the workspace and
+//                  clears the status word and the run list
 //   k_dist_params  scan of tile sums; per distribution W, reciprocal, G0
-//   k_build_tile keys, levels, node records, guide-table entries per tile
-//   k_fixup      deferred node records and long guide-table runs
+//   k_build_tile   keys, levels, node records, guide-table entries per tile
+//   k_fixup        deferred node records and long guide-table runs
 #include "rtf_internal.h"
 
 namespace rtf {
