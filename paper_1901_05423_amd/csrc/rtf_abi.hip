@@ -112,6 +112,7 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     a.defer_count = reinterpret_cast<int32_t *>(b + L.dcnt);
     a.defer_items = reinterpret_cast<int32_t *>(b + L.ditems);
     a.run_count = reinterpret_cast<uint64_t *>(b + L.status + 64);  // in the status block
+    a.item_count = reinterpret_cast<uint32_t *>(b + L.status + 72);
     a.runs = reinterpret_cast<Run *>(b + L.runs);
     if (launch_build(a, st) != hipSuccess) return RTF_ERR_HIP;
     *out = f;

@@ -365,6 +365,7 @@ __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
         if (tid == 0) {
             *a.status = 0u;
             *a.run_count = 0;
+            *a.item_count = 0u;
         }
         for (int64_t q = tid; q <= a.D; q += BT) {
             a.elem_off[q] = BATCHED ? a.src_elem_off[q] : (q ? a.n_total : 0);
@@ -494,6 +495,7 @@ struct alignas(16) TileSmem {
     int64_t c_begin;
     int32_t win_hi;  // highest window position phase 4 wrote
     int32_t ndefer;
+    int32_t item_base;  // this tile's place in the grid-wide deferral list
     int32_t items[DEFER_CAP];
 };
 
@@ -856,10 +858,15 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_
         else if (kind == WIN_HEAD) store_covered(a.cells, c, sm.key[li - 1], sm.key[li], g - 1);
         else store_covered(a.cells, c, sm.key[li], KEY_END, g);
     }
+    // the deferred nodes join one grid-wide list (a tile with more than
+    // DEFER_CAP of them is redone whole by the fix-up instead)
     const int32_t nd = sm.ndefer;
     if (tid == 0) a.defer_count[t] = nd;
-    const int32_t nk = nd < DEFER_CAP ? nd : DEFER_CAP;
-    for (int32_t q = tid; q < nk; q += BT) a.defer_items[t * DEFER_CAP + q] = sm.items[q];
+    if (nd > 0 && nd <= DEFER_CAP) {  // uniform across the block
+        if (tid == 0) sm.item_base = (int32_t)atomicAdd(a.item_count, (uint32_t)nd);
+        __syncthreads();
+        for (int32_t q = tid; q < nd; q += BT) a.defer_items[sm.item_base + q] = sm.items[q];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1059,71 +1066,56 @@ struct GlobalView {
 template <bool BATCHED>
 __device__ void fixup_tile(const BuildArgs &a, int64_t t);
 
-// Each block takes a contiguous range of tiles and reads their deferral
-// counts in parallel; most tiles defer nothing.  The listed nodes of all the
-// range's tiles are gathered in LDS and fixed together: one wave per node
-// while they are few (the searches then take 64 probes per step), one
-// thread per node otherwise.  A tile that kept no list redoes all its nodes,
-// one thread each.  Then every wave of the grid fills an equal share of the
-// cells of the listed guide-table runs.
-constexpr int ITEM_CAP = 1024;
-constexpr int WAVE_ITEMS = 32;
+// The deferred nodes of all tiles are one list: while it is short, each
+// wave of the grid takes one node at a time (its searches then take 64
+// probes per step), else each thread does.  Each block also reads the
+// deferral counts of a contiguous range of tiles in parallel and redoes, one
+// thread per node, a tile that deferred more than it could list.  Then every
+// wave fills an equal share of the cells of the listed guide-table runs.
 template <bool BATCHED>
 __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
     constexpr int NW = BT / 64;
-    __shared__ int32_t s_item[ITEM_CAP], s_itile[ITEM_CAP];
     __shared__ int32_t s_list[BT];
-    __shared__ uint64_t s_wave[NW];
-    __shared__ int32_t s_n, s_nt;
+    __shared__ int32_t s_nt;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * NW, gw = (int64_t)blockIdx.x * NW + wid;
+    auto dist_of = [&](int64_t j) -> const Dist & {
+        const int64_t tq = j / TILE;  // a listed node belongs to the tile that deferred it
+        return a.dists[BATCHED ? find_segment_in(a.elem_off, a.tile_dist[tq], a.tile_dist[tq + 1] + 1, j) : 0];
+    };
+    const int64_t ni = *a.item_count;
+    if (ni <= 2 * nwaves) {
+        for (int64_t q = gw; q < ni; q += nwaves) {
+            const int64_t j = a.defer_items[q];
+            GlobalView<BATCHED> gv(a, dist_of(j));
+            uint64_t kj;
+            int32_t c0, c1;
+            const bool first = gv.node_wave(j, kj, c0, c1);
+            if (lane == 0) {
+                if (first) gv.root_cell(j, c1);
+                store_node(a.nodes, j, kj, c0, c1);
+            }
+        }
+    } else {
+        for (int64_t q = (int64_t)blockIdx.x * BT + tid; q < ni; q += (int64_t)gridDim.x * BT) {
+            const int64_t j = a.defer_items[q];
+            GlobalView<BATCHED> gv(a, dist_of(j));
+            uint64_t kj;
+            int32_t c0, c1;
+            if (gv.node(j, kj, c0, c1)) gv.root_cell(j, c1);
+            store_node(a.nodes, j, kj, c0, c1);
+        }
+    }
     const int64_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
     const int64_t t_lo = (int64_t)blockIdx.x * per;
     const int64_t t_hi = t_lo + per < a.ntiles ? t_lo + per : a.ntiles;
     for (int64_t t0 = t_lo; t0 < t_hi; t0 += BT) {
-        if (tid == 0) {
-            s_n = 0;
-            s_nt = 0;
-        }
-        const int64_t t = t0 + tid;
-        const int32_t cnt = t < t_hi ? a.defer_count[t] : 0;
-        const int32_t listed = cnt <= DEFER_CAP ? cnt : 0;
-        uint64_t total;
-        const int64_t at = (int64_t)block_excl_scan<NW>((uint64_t)listed, s_wave, total);  // has barriers
-        if (cnt > DEFER_CAP || (listed > 0 && at + listed > ITEM_CAP)) {
-            s_list[atomicAdd(&s_nt, 1)] = tid;
-        } else if (listed > 0) {
-            for (int32_t q = 0; q < listed; ++q) {
-                s_item[at + q] = a.defer_items[t * DEFER_CAP + q];
-                s_itile[at + q] = (int32_t)(t - t0);
-            }
-            atomicMax(&s_n, (int32_t)(at + listed));
-        }
+        if (tid == 0) s_nt = 0;
         __syncthreads();
-        const int32_t ni = s_n, nt = s_nt;
-        if (ni <= WAVE_ITEMS) {
-            for (int32_t q = wid; q < ni; q += NW) {
-                const int64_t j = s_item[q], tq = t0 + s_itile[q];
-                const Dist &P = a.dists[BATCHED ? find_segment_in(a.elem_off, a.tile_dist[tq], a.tile_dist[tq + 1] + 1, j) : 0];
-                GlobalView<BATCHED> gv(a, P);
-                uint64_t kj;
-                int32_t c0, c1;
-                const bool first = gv.node_wave(j, kj, c0, c1);
-                if (lane == 0) {
-                    if (first) gv.root_cell(j, c1);
-                    store_node(a.nodes, j, kj, c0, c1);
-                }
-            }
-        } else {
-            for (int32_t q = tid; q < ni; q += BT) {
-                const int64_t j = s_item[q], tq = t0 + s_itile[q];
-                const Dist &P = a.dists[BATCHED ? find_segment_in(a.elem_off, a.tile_dist[tq], a.tile_dist[tq + 1] + 1, j) : 0];
-                GlobalView<BATCHED> gv(a, P);
-                uint64_t kj;
-                int32_t c0, c1;
-                if (gv.node(j, kj, c0, c1)) gv.root_cell(j, c1);
-                store_node(a.nodes, j, kj, c0, c1);
-            }
-        }
+        const int64_t t = t0 + tid;
+        if (t < t_hi && a.defer_count[t] > DEFER_CAP) s_list[atomicAdd(&s_nt, 1)] = tid;
+        __syncthreads();
+        const int32_t nt = s_nt;
         for (int32_t q = 0; q < nt; ++q) fixup_tile<BATCHED>(a, t0 + s_list[q]);
         __syncthreads();
     }
@@ -1132,7 +1124,6 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
     const int64_t cap = run_cap(a.m_total);
     const int64_t nrun = (int64_t)(rc >> 32);
     const int64_t total = nrun > 0 && nrun <= cap ? (int64_t)(uint32_t)rc : 0;  // else flagged
-    const int64_t nwaves = (int64_t)gridDim.x * NW, gw = (int64_t)blockIdx.x * NW + wid;
     int64_t p = total * gw / nwaves;
     const int64_t p_end = total * (gw + 1) / nwaves;
     if (p >= p_end) return;
@@ -1161,14 +1152,12 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
 
 template <bool BATCHED>
 __device__ void fixup_tile(const BuildArgs &a, int64_t t) {
-    const int32_t cnt = a.defer_count[t];
+    // more deferrals than a tile lists: redo every node record of the tile
     const int64_t base = t * TILE;
     const int32_t d_lo = BATCHED ? a.tile_dist[t] : 0, d_hi = BATCHED ? a.tile_dist[t + 1] : 0;
-    // more deferrals than were kept: redo every node record of the tile
-    const bool all = cnt > DEFER_CAP;
-    const int64_t count = all ? (a.n_total - base < TILE ? a.n_total - base : TILE) : cnt;
+    const int64_t count = a.n_total - base < TILE ? a.n_total - base : TILE;
     for (int64_t k = threadIdx.x; k < count; k += BT) {
-        const int64_t j = all ? base + k : (int64_t)a.defer_items[t * DEFER_CAP + k];
+        const int64_t j = base + k;
         const Dist &P = a.dists[BATCHED ? find_segment_in(a.elem_off, d_lo, d_hi + 1, j) : 0];
         GlobalView<BATCHED> gv(a, P);
         uint64_t kj;

@@ -117,7 +117,8 @@ struct BuildArgs {
     uint64_t *tile_prefix;  // [ntiles]
     uint64_t *dist_local;   // [D]: in-tile prefix at each distribution start
     int32_t *defer_count;   // [ntiles]
-    int32_t *defer_items;   // [ntiles * DEFER_CAP]: deferred node indices
+    int32_t *defer_items;   // [ntiles * DEFER_CAP]: the deferred nodes of all tiles, one list
+    uint32_t *item_count;   // length of that list
     int32_t *tile_dist;     // [ntiles + 2]: distribution of element min(t TILE, n - 1)
     uint64_t *run_count;    // (runs listed << 32) | cells they cover
     Run *runs;              // [run_cap(m_total)]
