@@ -26,6 +26,27 @@ __device__ inline int32_t block_find_segment(const int64_t *off, int32_t D, int6
 }
 
 constexpr int SCHUNK = 256 * 8;  // samples per block step of the batched kernel
+constexpr int CHUNK_DISTS = 256;  // distributions a chunk can stage in LDS
+
+static_assert(sizeof(Dist) == 64, "a staged record is four 16-byte words");
+__device__ inline Dist lds_dist(const uint4 *s_dist, int32_t k) {
+    Dist P;
+    uint4 *q = reinterpret_cast<uint4 *>(&P);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) q[w] = s_dist[4 * k + w];
+    return P;
+}
+
+// index k in [lo, hi) with off[k] <= i < off[k+1], given off[lo] <= i < off[hi]
+// (off may hold equal neighbours; the last k with off[k] <= i is taken)
+__device__ inline int32_t find_segment_in(const int64_t *off, int32_t lo, int32_t hi, int64_t i) {
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 __device__ inline Node load_node(const Node *nodes, int64_t j) {
     uint4 v = *reinterpret_cast<const uint4 *>(nodes + j);
@@ -182,6 +203,8 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
             one(s, dists[0]);
         return;
     }
+    __shared__ int64_t s_soff[256];
+    __shared__ uint4 s_dist[4 * CHUNK_DISTS];
     // batched: a block takes chunks of SCHUNK consecutive samples (numbered
     // per XCD, so that one XCD's L2 serves a few neighbouring distributions),
     // finds the chunk's first distribution once (block-wide), and each lane
@@ -229,6 +252,30 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
             }
             continue;
         }
+        // Several distributions: thread k reads offset d + k, and those below
+        // the chunk's end count the distributions starting inside it.  With
+        // fewer than CHUNK_DISTS of them their offsets and parameters are
+        // staged in LDS, and each sample finds its own by a search there;
+        // otherwise each lane walks the offsets in global memory.
+        const int64_t ok = sample_off[d + (int32_t)threadIdx.x <= D ? d + (int32_t)threadIdx.x : D];
+        s_soff[threadIdx.x] = ok;
+        const int nb = __syncthreads_count(threadIdx.x > 0 && d + (int32_t)threadIdx.x <= D && ok < cend);
+        if (nb < CHUNK_DISTS - 1) {  // offsets d .. d + nb + 1 held, the last at or past cend
+            const uint4 *src = reinterpret_cast<const uint4 *>(dists + d);
+            for (int q = threadIdx.x; q < 4 * (nb + 1); q += 256) s_dist[q] = src[q];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < SCHUNK / 256; k += 2) {
+                const int64_t sa = c0 + threadIdx.x + 256 * k, sb = sa + 256;
+                if (sa >= cend) break;
+                const bool has_b = sb < cend;
+                const int32_t ka = find_segment_in(s_soff, 0, nb + 1, sa);
+                const int32_t kb = has_b ? find_segment_in(s_soff, ka, nb + 1, sb) : ka;
+                two(sa, sb, has_b, lds_dist(s_dist, ka), lds_dist(s_dist, kb));
+            }
+            __syncthreads();  // before the next chunk restages
+            continue;
+        }
 #pragma unroll
         for (int k = 0; k < SCHUNK / 256; k += 2) {
             const int64_t sa = c0 + threadIdx.x + 256 * k, sb = sa + 256;
@@ -240,6 +287,7 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
                 while (sb >= dend) dend = sample_off[++d + 1];
             two(sa, sb, has_b, dists[da], dists[d]);
         }
+        __syncthreads();  // s_soff is rewritten by the next chunk
     }
 }
 
