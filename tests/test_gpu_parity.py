@@ -249,6 +249,17 @@ def test_single_tree_large(rtf, orc):
     build_and_compare(rtf, orc, w, 600, S_extra=20000, seed=6)
 
 
+def test_many_deferrals(rtf, orc):
+    """Cells of several tiles each: every tile defers the nodes whose
+    subtrees leave it, tens of thousands in all, more than the fix-up's
+    waves take one at a time, so its one-thread-per-node path runs too."""
+    note("many deferrals n=2^22")
+    rng = np.random.default_rng(33)
+    w = random_weights(rng, 1 << 22)
+    build_and_compare(rtf, orc, w, 512, S_extra=20000, seed=7, baselines=False)
+    build_and_compare(rtf, orc, w, 2048, S_extra=20000, seed=8, baselines=False)
+
+
 def test_deferral_overflow(rtf, orc):
     """Long runs of equal keys (zero weights) inside one cell make every node
     of a tile defer, which overflows the per-tile list."""
