@@ -95,6 +95,19 @@ def test_batched_zero_distribution(rtf, orc):
         assert np.array_equal(idx[10 * d:10 * d + 10], i_ref)
 
 
+def test_batched_many_tiny(rtf, orc):
+    """Thousands of tiny distributions with a few uniforms each, so that a
+    chunk of the sampling kernel spans more distributions than it can stage
+    and its lanes walk the offsets; some get no uniform at all."""
+    note("batched D=3000 tiny")
+    rng = np.random.default_rng(25)
+    sizes = rng.integers(1, 6, 3000)
+    ws = [random_weights(rng, int(s)) for s in sizes]
+    counts = rng.integers(0, 4, 3000)
+    counts[1000:1100] = 300  # a stretch that chunks can stage
+    check_batched(rtf, orc, ws, [int(s) for s in sizes], counts, 4)
+
+
 def test_batched_staged_cells(rtf, orc):
     """Batches with several samples per cell run the kernel that stages a
     distribution's cells in LDS: distributions of at most 1024 cells staged,
