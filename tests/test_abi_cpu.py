@@ -94,6 +94,21 @@ def test_argument_errors_before_launch(L):
         assert L.rtf_status_string(c).decode().startswith("RTF_")
 
 
+def test_empty_sample_batches_are_no_ops(L):
+    """S = 0 is valid: nothing is launched and null buffers are accepted; a
+    negative count is an argument error."""
+    import paper_1901_05423_amd as rtf
+    f2 = rtf.rtf_forest(D=2, tile=2048, n_total=10, m_total=10, nodes=0x100000,
+                        cells=0x100000, dists=0x100000, status=0x100000)
+    f1 = rtf.rtf_forest(D=1, tile=2048, n_total=10, m_total=10, nodes=0x100000,
+                        cells=0x100000, dists=0x100000, status=0x100000)
+    P = ctypes.c_void_p
+    assert L.rtf_sample(ctypes.byref(f1), None, 0, None, None, None) == rtf.RTF_OK
+    assert L.rtf_sample_batched(ctypes.byref(f2), P(0x100000), None, 0, None, None, None) == rtf.RTF_OK
+    assert L.rtf_sample_2d(ctypes.byref(f2), None, 0, None, None, None) == rtf.RTF_OK
+    assert L.rtf_sample(ctypes.byref(f1), None, -1, None, None, None) == rtf.RTF_ERR_INVALID_ARG
+
+
 def test_fixed_point_helpers_exact(tmp_path):
     src = os.path.join(ROOT, "tests", "native", "fixed_point_check.hip")
     exe = str(tmp_path / "fixed_point_check")
