@@ -90,11 +90,6 @@ __device__ inline int32_t find_segment_in(const int64_t *off, int32_t lo, int32_
     return lo;
 }
 
-// index d with off[d] <= i < off[d+1] over off[0..D]
-__device__ inline int32_t find_segment(const int64_t *off, int32_t D, int64_t i) {
-    return find_segment_in(off, 0, D, i);
-}
-
 // first d in [0, D] with off[d] > i (off[0..D] non-decreasing)
 __device__ inline int32_t upper_bound(const int64_t *off, int32_t D, int64_t i) {
     int32_t lo = 0, hi = D + 1;

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
 
 // One distribution: a fixed grid strides over the weights with 16-byte
 // loads, so only a few thousand blocks reach the atomic.
-constexpr int QMAX_BLOCKS = 2048;
+constexpr int QMAX_BLOCKS = 1024;  // fewer blocks, fewer atomics on the one maximum
 __global__ __launch_bounds__(QT) void k_qmax_single(const float *__restrict__ v, int64_t n,
                                                     bool vec, double *scale, uint32_t *status) {
     __shared__ uint32_t s_max[QT / 64];
@@ -158,12 +158,23 @@ __global__ __launch_bounds__(QT) void k_qmax_single(const float *__restrict__ v,
     const int64_t stride = (int64_t)gridDim.x * QT;
     const int64_t n4 = vec ? n / 4 : 0;
     const float4 *v4 = reinterpret_cast<const float4 *>(v);
-    for (int64_t i = (int64_t)blockIdx.x * QT + threadIdx.x; i < n4; i += stride) {
-        const float4 x = v4[i];
-        take(x.x);
-        take(x.y);
-        take(x.z);
-        take(x.w);
+    // four 16-byte loads per thread in flight; an index past the end is
+    // clamped to the last vector, which a maximum may read twice
+    constexpr int QU = 4;
+    for (int64_t i0 = (int64_t)blockIdx.x * QT + threadIdx.x; i0 < n4; i0 += stride * QU) {
+        float4 xq[QU];
+#pragma unroll
+        for (int k = 0; k < QU; ++k) {
+            const int64_t i = i0 + stride * k;
+            xq[k] = v4[i < n4 ? i : n4 - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < QU; ++k) {
+            take(xq[k].x);
+            take(xq[k].y);
+            take(xq[k].z);
+            take(xq[k].w);
+        }
     }
     for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * QT + threadIdx.x; i < n; i += stride) take(v[i]);
     if (bad) s_bad = 1;
