@@ -586,7 +586,7 @@ __device__ inline void root_cell_record(const TileSmem &sm, Cell *cells, int64_t
 // distribution parameters) is issued before the block scan and none sits
 // under a branch, so a block waits for one round trip.  FULL: the tile lies
 // inside [0, n) and the weights are 16-byte aligned.
-template <bool BATCHED, bool FULL>
+template <bool BATCHED, bool FULL, bool UNI>
 __device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
     const int tid = threadIdx.x;
     const int64_t base = t * TILE;
@@ -604,12 +604,13 @@ __device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
     uint32_t wv[ITEMS];
     load_items<FULL>(a.w, i0, n, wv);
     const uint64_t tp = a.tile_prefix[t];
-    // the distributions of the tile's elements lie in [d_lo, d_hi]
+    // the distributions of the tile's elements lie in [d_lo, d_hi]; UNI: in
+    // one distribution, whose parameters are then uniform (scalar registers)
     int32_t dcur = 0, d_lo = 0, d_hi = 0;
     if (BATCHED) {
         d_lo = a.tile_dist[t];
         d_hi = a.tile_dist[t + 1];
-        dcur = find_segment_in(a.elem_off, d_lo, d_hi + 1, i0 < n ? i0 : n - 1);
+        dcur = UNI ? d_lo : find_segment_in(a.elem_off, d_lo, d_hi + 1, i0 < n ? i0 : n - 1);
     }
     Dist P = a.dists[dcur];
     const uint64_t hw = hexists ? hraw : 0u;
@@ -635,7 +636,7 @@ __device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
         L.key = 0;
         L.cell = -2;
         if (e < live) {
-            if (BATCHED) {
+            if (BATCHED && !UNI) {
                 while (i0 + e >= dend) {
                     ++dcur;
                     P = a.dists[dcur];
@@ -679,8 +680,16 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_
     if (tid == 0) sm.ndefer = 0;
 
     // ---- phase 1: keys and cells of the tile's leaves -----------------------
-    if (vec && base + TILE <= n) build_keys<BATCHED, true>(a, sm, t);
-    else build_keys<BATCHED, false>(a, sm, t);
+    // a tile inside one distribution (the common case) takes the phase with
+    // uniform parameters
+    const bool full = vec && base + TILE <= n;
+    if (!BATCHED || d_lo == d_hi) {
+        if (full) build_keys<BATCHED, true, true>(a, sm, t);
+        else build_keys<BATCHED, false, true>(a, sm, t);
+    } else {
+        if (full) build_keys<BATCHED, true, false>(a, sm, t);
+        else build_keys<BATCHED, false, false>(a, sm, t);
+    }
     __syncthreads();
 
     // ---- phase 2: levels of all boundaries held; empty slots and window ----
