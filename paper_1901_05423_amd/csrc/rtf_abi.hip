@@ -39,7 +39,7 @@ Layout make_layout(int32_t D, int64_t n, int64_t m) {
     L.tsum = o;
     o = align256(o + sizeof(uint64_t) * (size_t)L.ntiles);
     L.tpre = o;
-    o = align256(o + sizeof(uint64_t) * (size_t)L.ntiles);
+    o = align256(o + sizeof(uint64_t) * (size_t)(L.ntiles + 1));  // + the grand total
     L.dloc = o;
     o = align256(o + sizeof(uint64_t) * (size_t)D);
     L.tdist = o;

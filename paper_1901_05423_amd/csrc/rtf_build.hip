@@ -18,6 +18,7 @@
 //                  starts); block 0 copies the offsets into the workspace and
 //                  clears the status word and the run list
 //   k_dist_params  scan of tile sums; per distribution W, reciprocal, G0
+//   k_dist_finish  the latter for more than PT distributions
 //   k_build_tile   keys, levels, node records, guide-table entries per tile
 //   k_fixup        deferred node records and long guide-table runs
 #include "rtf_internal.h"
@@ -375,9 +376,43 @@ __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
 // ---------------------------------------------------------------------------
 // k_dist_params: one block.  Exclusive scan of the tile sums, then per
 // distribution the total W, the divisor normalisation and reciprocal, and the
-// global prefix at its first element.
+// global prefix at its first element; more than PT distributions are left to
+// k_dist_finish, one thread each over many blocks.
 // ---------------------------------------------------------------------------
 constexpr int PT = 1024;
+
+// Distribution d's parameters: the total W, the divisor normalisation and
+// reciprocal, and the global prefix at its first element.
+template <bool BATCHED>
+__device__ inline void dist_params_of(const BuildArgs &a, int32_t d, uint64_t total) {
+    const int64_t eo = a.elem_off[d], e1 = a.elem_off[d + 1];
+    uint64_t G0 = 0, G1 = total;
+    if (BATCHED) {
+        G0 = a.tile_prefix[eo / TILE] + a.dist_local[d];
+        if (d + 1 < a.D) G1 = a.tile_prefix[e1 / TILE] + a.dist_local[d + 1];
+    }
+    Dist P;
+    P.W = G1 - G0;
+    P.G0 = G0;
+    P.eo = eo;
+    P.n = e1 - eo;
+    P.co = a.cell_off[d];
+    P.m = a.cell_off[d + 1] - P.co;
+    P.flags = 0;
+    if (P.W == 0) {
+        P.s = 0;
+        P.v = 0;
+        P.flags = DIST_ZERO;
+        atomicOr(a.status, status_bit(RTF_ERR_ZERO_TOTAL));
+    } else {
+        P.s = (uint32_t)clz64(P.W);
+        P.v = reciprocal_2by1(P.W << P.s);
+    }
+    if (P.m > 1 && (P.m & (P.m - 1)) == 0)
+        P.flags |= (uint32_t)(64 - __builtin_ctzll((uint64_t)P.m)) << DIST_SHIFT_BIT;
+    a.dists[d] = P;
+}
+
 template <bool BATCHED>
 __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
     __shared__ uint64_t s_wave[PT / 64];
@@ -413,36 +448,19 @@ __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
         carry += round_total;
     }
     const uint64_t total = carry;
+    if (a.D > PT) {  // k_dist_finish takes the distributions, one thread each
+        if (threadIdx.x == 0) a.tile_prefix[nt] = total;
+        return;
+    }
     __threadfence_block();
     __syncthreads();
-    for (int32_t d = threadIdx.x; d < a.D; d += PT) {
-        int64_t eo = a.elem_off[d], e1 = a.elem_off[d + 1];
-        uint64_t G0 = 0, G1 = total;
-        if (BATCHED) {
-            G0 = a.tile_prefix[eo / TILE] + a.dist_local[d];
-            if (d + 1 < a.D) G1 = a.tile_prefix[e1 / TILE] + a.dist_local[d + 1];
-        }
-        Dist P;
-        P.W = G1 - G0;
-        P.G0 = G0;
-        P.eo = eo;
-        P.n = e1 - eo;
-        P.co = a.cell_off[d];
-        P.m = a.cell_off[d + 1] - P.co;
-        P.flags = 0;
-        if (P.W == 0) {
-            P.s = 0;
-            P.v = 0;
-            P.flags = DIST_ZERO;
-            atomicOr(a.status, status_bit(RTF_ERR_ZERO_TOTAL));
-        } else {
-            P.s = (uint32_t)clz64(P.W);
-            P.v = reciprocal_2by1(P.W << P.s);
-        }
-        if (P.m > 1 && (P.m & (P.m - 1)) == 0)
-            P.flags |= (uint32_t)(64 - __builtin_ctzll((uint64_t)P.m)) << DIST_SHIFT_BIT;
-        a.dists[d] = P;
-    }
+    if ((int32_t)threadIdx.x < a.D) dist_params_of<BATCHED>(a, (int32_t)threadIdx.x, total);
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(256) void k_dist_finish(BuildArgs a) {
+    const int32_t d = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+    if (d < a.D) dist_params_of<BATCHED>(a, d, a.tile_prefix[a.ntiles]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1182,6 +1200,8 @@ hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
     if (a.D > 1) {
         hipLaunchKernelGGL(k_tile_sums<true>, sumgrid, dim3(BT), 0, st, a, vec);
         hipLaunchKernelGGL(k_dist_params<true>, dim3(1), dim3(PT), 0, st, a);
+        if (a.D > PT)
+            hipLaunchKernelGGL(k_dist_finish<true>, dim3((unsigned)((a.D + 255) / 256)), dim3(256), 0, st, a);
         hipLaunchKernelGGL(k_build_tile<true>, grid, dim3(BT), 0, st, a, vec);
         hipLaunchKernelGGL(k_fixup<true>, fixgrid, dim3(BT), 0, st, a);
     } else {

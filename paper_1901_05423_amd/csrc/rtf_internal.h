@@ -114,7 +114,7 @@ struct BuildArgs {
     Dist *dists;
     uint32_t *status;
     uint64_t *tile_sum;     // [ntiles]
-    uint64_t *tile_prefix;  // [ntiles]
+    uint64_t *tile_prefix;  // [ntiles + 1], the last the grand total
     uint64_t *dist_local;   // [D]: in-tile prefix at each distribution start
     int32_t *defer_count;   // [ntiles]
     int32_t *defer_items;   // [ntiles * DEFER_CAP]: the deferred nodes of all tiles, one list
