@@ -36,6 +36,42 @@ __device__ inline int32_t block_find_segment(const int64_t *off, int32_t D, int6
     return lo;
 }
 
+// Both d0 with off[d0] <= i0 < off[d0+1] and d1 with off[d1] <= i1 <
+// off[d1+1] (uniform i0 <= i1), found at once: waves 0-1 search for i0 and
+// waves 2-3 for i1, 128 probes per round each, so 10^4 distributions take two
+// rounds for both.  Every thread must call it; s_cnt holds 2 x 4 counts.
+__device__ inline void block_find_two(const int64_t *off, int32_t D, int64_t i0, int64_t i1,
+                                      int32_t *s_cnt, int32_t &d0, int32_t &d1) {
+    static_assert(QT == 256, "four waves, two per search");
+    const int w = threadIdx.x >> 6, t = threadIdx.x & 127;
+    const bool second = w >= 2;
+    const int64_t i = second ? i1 : i0;
+    int32_t lo0 = 0, hi0 = D, lo1 = 0, hi1 = D;  // off[lo] <= i < off[hi]
+    for (int round = 0; hi0 - lo0 > 1 || hi1 - lo1 > 1; ++round) {
+        const int32_t lo = second ? lo1 : lo0, hi = second ? hi1 : hi0;
+        const int32_t step = (hi - lo + 127) / 128;
+        const int32_t p = lo + (t + 1) * step;
+        const bool below = hi - lo > 1 && p < hi && off[p] <= i;
+        const int32_t c = __popcll(__ballot(below));
+        int32_t *cnt = s_cnt + 4 * (round & 1);  // alternate, so one barrier a round
+        if ((threadIdx.x & 63) == 0) cnt[w] = c;
+        __syncthreads();
+        const int32_t step0 = (hi0 - lo0 + 127) / 128, step1 = (hi1 - lo1 + 127) / 128;
+        if (hi0 - lo0 > 1) {
+            const int32_t n0 = lo0 + (cnt[0] + cnt[1]) * step0;
+            hi0 = n0 + step0 < hi0 ? n0 + step0 : hi0;
+            lo0 = n0;
+        }
+        if (hi1 - lo1 > 1) {
+            const int32_t n1 = lo1 + (cnt[2] + cnt[3]) * step1;
+            hi1 = n1 + step1 < hi1 ? n1 + step1 : hi1;
+            lo1 = n1;
+        }
+    }
+    d0 = lo0;
+    d1 = lo1;
+}
+
 __device__ inline uint32_t *max_word(double *scale, int32_t d) {
     return reinterpret_cast<uint32_t *>(scale + d);
 }
@@ -54,6 +90,7 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
                                              int64_t n, double *scale, uint32_t *status) {
     __shared__ uint32_t s_max[QT / 64];
     __shared__ uint32_t s_dmax[QMAX_LDS_DISTS];
+    __shared__ int32_t s_cnt[8];
     __shared__ int s_bad;
     const int64_t b0 = (int64_t)blockIdx.x * QT * QI;
     const int64_t b1 = b0 + (int64_t)QT * QI < n ? b0 + (int64_t)QT * QI : n;
@@ -65,8 +102,8 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
         const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
         xs[k] = v[i < n ? i : n - 1];
     }
-    const int32_t dfirst = off ? block_find_segment(off, D, b0) : 0;
-    const int32_t dlast = off ? block_find_segment(off, D, b1 - 1) : 0;
+    int32_t dfirst = 0, dlast = 0;
+    if (off) block_find_two(off, D, b0, b1 - 1, s_cnt, dfirst, dlast);
     const bool one = dlast == dfirst;
     // a block over a few distributions collects their maxima in LDS and adds
     // each to global memory once; only one over very many uses global atomics
