@@ -260,6 +260,29 @@ __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t 
 }
 
 // ---------------------------------------------------------------------------
+// The first d in [0, D] with off[d] > i (D + 1 if none; off[0..D]
+// non-decreasing), found by one wave (uniform i): each step probes 64 evenly
+// spaced offsets and keeps the bracket between the last one at or below i
+// and the first above it.  Every lane of the wave must call it.
+__device__ inline int32_t wave_upper_bound(const int64_t *off, int32_t D, int64_t i) {
+    const int32_t lane = threadIdx.x & 63;
+    int32_t lo = 0, hi = D + 1;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int32_t step = (hi - lo + 63) / 64;
+        const int32_t p = lo + lane * step;
+        const int32_t cnt = __popcll(__ballot(p < hi && off[p] <= i));  // a prefix of the lanes
+        if (cnt == 0) {
+            hi = lo;
+        } else {
+            const int32_t last = lo + (cnt - 1) * step;  // off[last] <= i
+            const int32_t next = lo + cnt * step;       // off[next] > i, or next >= hi
+            lo = last + 1;
+            hi = next < hi ? next : hi;
+        }
+    }
+    return lo;
+}
+
 // k_tile_sums: the prefix-sum pass over the weights (Sec. 2.6 notes that the
 // prefix sum of an inversion method computes efficiently in parallel)
 // ---------------------------------------------------------------------------
@@ -305,23 +328,31 @@ __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *
         }
         return;
     }
-    // per tile, two searches over the caller's offsets, all in parallel: the
-    // first distribution starting at or after the tile's first element
-    // (lanes 0..TS_TILES-1), and the distribution holding that element
-    // (lanes TS_TILES..2 TS_TILES-1, into tile_dist); the block of the last
-    // tile also fills tile_dist[ntiles] and tile_dist[ntiles + 1]
-    if (tid < 2 * TS_TILES + 1) {
-        const int k = tid < 2 * TS_TILES ? tid % TS_TILES : 0;
-        const int64_t t = tid < 2 * TS_TILES ? t0 + k : a.ntiles;
-        const int64_t i = t * TILE < a.n_total ? t * TILE : a.n_total - 1;
-        if (tid < TS_TILES) {
-            if (t < a.ntiles) s_first[k] = lower_bound(a.src_elem_off, a.D, t * TILE);
-        } else if (tid < 2 * TS_TILES) {
-            if (t < a.ntiles) a.tile_dist[t] = upper_bound(a.src_elem_off, a.D, i) - 1;
-        } else if (t0 + TS_TILES >= a.ntiles) {
-            const int32_t d = upper_bound(a.src_elem_off, a.D, i) - 1;
-            a.tile_dist[a.ntiles] = d;
-            a.tile_dist[a.ntiles + 1] = d;
+    // per tile, two searches over the caller's offsets, one whole wave each
+    // and all eight at once (64 probes per step: three steps for 10^4
+    // distributions): the first distribution starting at or after the tile's
+    // first element (waves 0..TS_TILES-1), and the distribution holding that
+    // element (waves TS_TILES..2 TS_TILES-1, into tile_dist); the block of the
+    // last tile also fills tile_dist[ntiles] and tile_dist[ntiles + 1]
+    static_assert(2 * TS_TILES == BT / 64, "one wave per search");
+    {
+        const int k = w % TS_TILES;
+        const int64_t t = t0 + k;
+        if (t < a.ntiles) {
+            if (w < TS_TILES) {
+                const int32_t d = wave_upper_bound(a.src_elem_off, a.D, t * TILE - 1);  // first off >= t*TILE
+                if (lane == 0) s_first[k] = d;
+            } else {
+                const int32_t d = wave_upper_bound(a.src_elem_off, a.D, t * TILE) - 1;
+                if (lane == 0) a.tile_dist[t] = d;
+            }
+        }
+        if (w == 0 && t0 + TS_TILES >= a.ntiles) {
+            const int32_t d = wave_upper_bound(a.src_elem_off, a.D, a.n_total - 1) - 1;
+            if (lane == 0) {
+                a.tile_dist[a.ntiles] = d;
+                a.tile_dist[a.ntiles + 1] = d;
+            }
         }
     }
 #pragma unroll
