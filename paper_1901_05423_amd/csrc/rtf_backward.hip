@@ -18,7 +18,7 @@ namespace rtf {
 
 namespace {
 
-constexpr int BB = 256;           // threads of the zeroing and combining kernels
+constexpr int CB = 1024;          // threads of the combining kernel (fewer chunk steps)
 constexpr int SB = 1024;          // threads of a scatter block
 constexpr int ILP = 2;            // samples a scatter thread loads at once
 constexpr int CHUNK = SB * 128;   // samples per scatter block
@@ -247,18 +247,18 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void k_
 }
 
 // One block per distribution: grad[k] = A - sum_{j>k} B_j - D_k, scanning the
-// distribution from its end in chunks of BB elements.
-__global__ __launch_bounds__(BB) void k_bcombine(const Dist *__restrict__ dists,
+// distribution from its end in chunks of CB elements.
+__global__ __launch_bounds__(CB) void k_bcombine(const Dist *__restrict__ dists,
                                                  const double *__restrict__ B,
                                                  const double *__restrict__ Dv,
                                                  const double *__restrict__ A,
                                                  double *__restrict__ grad) {
-    __shared__ double s_w[BB / 64];
+    __shared__ double s_w[CB / 64];
     const Dist P = dists[blockIdx.x];
     const double Ad = A[blockIdx.x];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double carry = 0.0;  // sum of B over elements after the current chunk
-    for (int64_t end = P.eo + P.n; end > P.eo; end -= BB) {
+    for (int64_t end = P.eo + P.n; end > P.eo; end -= CB) {
         // element handled by this thread: end-1-threadIdx.x (reverse order)
         const int64_t k = end - 1 - threadIdx.x;
         const bool ok = k >= P.eo;
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(BB) void k_bcombine(const Dist *__restrict__ dists,
         __syncthreads();
         double off = 0.0, tot = 0.0;
 #pragma unroll
-        for (int i = 0; i < BB / 64; ++i) {
+        for (int i = 0; i < CB / 64; ++i) {
             off += (i < w) ? s_w[i] : 0.0;
             tot += s_w[i];
         }
@@ -305,7 +305,7 @@ hipError_t launch_backward(const Node *nodes, const Dist *dists, int32_t D, int6
             hipLaunchKernelGGL(k_bscatter<false>, dim3((unsigned)nb), dim3(SB), 0, st, nodes, dists,
                                D, sample_off, u, idx, gx, S, scale, wsB, wsDv, wsA);
     }
-    hipLaunchKernelGGL(k_bcombine, dim3((unsigned)D), dim3(BB), 0, st, dists, wsB, wsDv, wsA,
+    hipLaunchKernelGGL(k_bcombine, dim3((unsigned)D), dim3(CB), 0, st, dists, wsB, wsDv, wsA,
                        grad_w);
     return hipGetLastError();
 }
