@@ -136,7 +136,9 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
             bad = true;
             continue;
         }
-        const uint32_t b = __float_as_uint(x);
+        // -0.0 passes the sign test; dropping the sign bit maps it to 0, so
+        // it cannot win the unsigned maximum over the positive weights
+        const uint32_t b = __float_as_uint(x) & 0x7fffffffu;
         mx = b > mx ? b : mx;
     }
     if (bad) s_bad = 1;
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(QT) void k_qmax_single(const float *__restrict__ v,
             bad = true;
             return;
         }
-        const uint32_t b = __float_as_uint(x);
+        const uint32_t b = __float_as_uint(x) & 0x7fffffffu;  // -0.0 counts as 0
         mx = b > mx ? b : mx;
     };
     const int64_t stride = (int64_t)gridDim.x * QT;

@@ -95,7 +95,7 @@ def logits(r: np.random.Generator, D: int = 256, n: int = 4096) -> np.ndarray:
     return r.standard_normal((D, n)).astype(np.float32)
 
 
-# The three densities of the paper's load-count table (Sec. 6), with index
+# The three densities of the paper's load-count table (Table 1, Sec. 4), with index
 # i = 0 .. n-1; each is normalised to a maximum of 1 in FP64 before the cast
 # to float32, so values below float32's range become zero weights.
 TABLE1_FAMILIES = ("pow20", "mod32_pow25", "mod64_pow35")

@@ -136,12 +136,14 @@ def test_batched_staged_cells(rtf, orc):
         assert_samples(idx[so[d]:so[d + 1]], x[so[d]:so[d + 1]], i_ref, x_ref)
 
 
-def test_c4_batched_uneven_full(rtf, orc):
+@pytest.mark.parametrize("ratio", [0.25, 1.0])
+def test_c4_batched_uneven_full(rtf, orc, ratio):
     """10,000 distributions, sizes log-uniform in [16, 65536], uniform or
-    Pareto(1.2) weights, ceil(64 n_d / 1000) uniforms each."""
+    Pareto(1.2) weights, ceil(64 n_d / 1000) uniforms each; guide cells
+    m_d = ratio n_d (the benchmark runs 1/4)."""
     import torch
     from paper_1901_05423_amd import workloads as wl
-    note("C4 batched D=10000")
+    note(f"C4 batched D=10000 ratio={ratio}")
     r = wl.rng(wl.C4_BATCHED)
     v, eo, so = wl.batched_uneven(r)
     u = wl.uniforms(r, int(so[-1]))
@@ -151,9 +153,10 @@ def test_c4_batched_uneven_full(rtf, orc):
     assert np.array_equal(s.cpu().numpy(), s_ref)
     note(f"C4 n_total={eo[-1]} S={so[-1]}: building")
     eod = to_dev(eo)
-    f = rtf.build_batched(q, eod, rtf.cells_like(eod))
+    cod = rtf.cells_like(eod, ratio)
+    f = rtf.build_batched(q, eod, cod)
     f.check()
-    ref = orc.forest(q_ref, elem_off=eo, cell_off=eo)
+    ref = orc.forest(q_ref, elem_off=eo, cell_off=cod.cpu().numpy())
     note("C4 oracle forest done")
     assert_forest(f, ref, "C4")
     idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
@@ -176,14 +179,15 @@ def quantised_map(orc, img, marginal):
     return v, q, eo
 
 
-def check_2d(rtf, orc, img, marginal, pairs, seed, zero_rows=False):
+def check_2d(rtf, orc, img, marginal, pairs, seed, zero_rows=False, ratio=1.0):
     rng = np.random.default_rng(seed)
     R, C = img.shape
     v, q_ref, eo = quantised_map(orc, img, marginal)
     q, _ = rtf.quantize(to_dev(v), to_dev(eo))
     assert np.array_equal(q.cpu().numpy(), q_ref)
     eod = to_dev(eo)
-    f = rtf.build_batched(q, eod, rtf.cells_like(eod))
+    cod = rtf.cells_like(eod, ratio)
+    f = rtf.build_batched(q, eod, cod)
     if zero_rows:  # an all-zero row is a distribution without mass
         import paper_1901_05423_amd as rtfm
         with pytest.raises(rtfm.RtfError):
@@ -207,7 +211,7 @@ def check_2d(rtf, orc, img, marginal, pairs, seed, zero_rows=False):
         lo = R + int(row) * C
         c_ref[sel], x_ref[sel] = orc.search(q_ref[lo:lo + C], u2[1::2][sel])
     assert_samples(rc[:, 1], xy[:, 1], c_ref, x_ref)
-    return f, q_ref, eo
+    return f, q_ref, eo, cod.cpu().numpy()
 
 
 def test_2d_small_map(rtf, orc):
@@ -228,15 +232,17 @@ def test_2d_two_pairs_per_lane(rtf, orc):
     check_2d(rtf, orc, img, marg, 9_000_001, 5)
 
 
-def test_c3_2d_full_map(rtf, orc):
+@pytest.mark.parametrize("ratio", [0.25, 1.0])
+def test_c3_2d_full_map(rtf, orc, ratio):
     """4096 x 4096 log-normal(0, 1.5) map with 8 hot spots: forest of the
-    marginal plus 4096 rows bit-exact, 2^20 pairs checked."""
+    marginal plus 4096 rows bit-exact at m_d = ratio n_d (the benchmark runs
+    1/4), 2^20 pairs checked."""
     from paper_1901_05423_amd import workloads as wl
-    note("C3 2D 4096x4096")
+    note(f"C3 2D 4096x4096 ratio={ratio}")
     img, marg = wl.map_2d(wl.rng(wl.C3_MAP_2D))
-    f, q_ref, eo = check_2d(rtf, orc, img, marg, 1 << 20, 4)
+    f, q_ref, eo, co = check_2d(rtf, orc, img, marg, 1 << 20, 4, ratio=ratio)
     note("C3 samples match; comparing forest")
-    assert_forest(f, orc.forest(q_ref, elem_off=eo, cell_off=eo), "C3")
+    assert_forest(f, orc.forest(q_ref, elem_off=eo, cell_off=co), "C3")
 
 
 def check_grad(rtf, orc, D, n, per, check_dists, seed, ratio=1.0):
@@ -357,6 +363,30 @@ def test_grad_block_paths(rtf, orc):
     raw_grad(rtf, orc, [big], [300000], 2)
     mixed = [small, big, (0.5 + rng.random(100)).astype(np.float32), np.ones(4096, np.float32)]
     raw_grad(rtf, orc, mixed, [262149, 140000, 7, 131072], 3)
+
+
+def test_grad_one_large_distribution(rtf, orc):
+    """One distribution of 2^22 weights and 2^24 samples: the combining pass
+    spreads it over 1024 chunks, each block adding the carry of the chunks
+    after it."""
+    note("grad one distribution n=2^22 S=2^24")
+    rng = np.random.default_rng(47)
+    v = (0.01 + rng.random(1 << 22)).astype(np.float32)
+    v[1000:1100] = 0
+    v[-5:] = 0
+    raw_grad(rtf, orc, [v], [1 << 24], 4)
+
+
+def test_grad_chunk_straddling(rtf, orc):
+    """Distributions that begin and end at and around the combining pass's
+    chunk edges (4096 elements), several inside one chunk and one over many."""
+    note("grad chunk straddling")
+    rng = np.random.default_rng(53)
+    sizes = [4096, 4095, 1, 2, 8192 + 3, 1, 70000, 17, 4096 * 3 - 24, 5]
+    vs = [(0.01 + rng.random(sz)).astype(np.float32) for sz in sizes]
+    counts = [int(c) for c in rng.integers(0, 50000, len(sizes))]
+    counts[3] = 0
+    raw_grad(rtf, orc, vs, counts, 6)
 
 
 def test_c5_grad_full(rtf, orc):

@@ -52,7 +52,7 @@ def test_load_stats_groups():
 
 
 def test_table1_trends(orc):
-    """The paper's load-count table (Sec. 6) on its three high-dynamic-range
+    """The paper's load-count table (Table 1, Sec. 4) on its three high-dynamic-range
     densities at n = m = 2^16 (the paper does not state its n and m): the
     Cutpoint maxima equal the printed 6 and 7 for the two periodic densities
     (they do not depend on n), and as the paper reports, the radix forest

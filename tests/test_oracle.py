@@ -163,6 +163,67 @@ def test_figure_keys_and_table(orc):
             assert len(cover) == 1 and f.table[g] == ~cover[0]
 
 
+SENT = 65  # level of a boundary that no merge crosses
+
+
+def test_figure_levels_from_labels(orc):
+    """Levels of Fig. radix_forest read off the drawing.
+
+    A leaf's printed digits are its lower bound's binary prefix down to the
+    split above it, so two neighbours in one cell first differ at printed
+    digit p, which is bit 64 - p of the 0.64 keys: level 65 - p (Sec. 3.1).
+    Neighbours in different cells (by the drawn cell lines) are SENT."""
+    w = figure_weights()
+    _, cells, labels, _ = load_forest_figure()
+    bars, _, _, _ = load_forest_figure()
+    # the cell of a leaf is the cell line interval its bar's left end lies in
+    width = cells[1] - cells[0]
+    cell = [int((bars[i][0] - cells[0]) // width + 1e-9) for i in range(12)]
+    cell[0] = 0
+    expect = []
+    for b in range(11):
+        if cell[b] != cell[b + 1]:
+            expect.append(SENT)
+            continue
+        da, db = labels[b].split(".")[1], labels[b + 1].split(".")[1]
+        p = next(k for k in range(min(len(da), len(db))) if da[k] != db[k]) + 1
+        expect.append(65 - p)
+    assert expect == [60, 59, 61, SENT, 62, SENT, SENT, 61, SENT, SENT, SENT]
+    assert orc.levels(w, 12).tolist() == expect
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_levels_brute_force(orc, seed):
+    """Levels against a bit-string comparison of exact keys: the first
+    differing binary digit of U_b and U_{b+1} (Sec. 3.1), SENT where the
+    cells differ (Sec. 3.2) and from the last positive weight on."""
+    rng = np.random.default_rng(9000 + seed)
+    n = int(rng.integers(2, 200))
+    w = random_weights(rng, n, zero_frac=[0, 0.3, 0.6, 0.1][seed % 4], skew=seed % 2 == 0)
+    if seed % 3 == 1:
+        w[-3:] = 0
+        if w.sum() == 0:
+            w[0] = 5
+    C = exact_prefix(w)
+    last = max(i for i in range(n) if w[i] > 0)
+    for m in {1, 3, n, 4 * n}:
+        lvl = orc.levels(w, m)
+        for b in range(n - 1):
+            if b + 1 > last:
+                assert lvl[b] == SENT, (b, m)
+                continue
+            Ua, Ub = exact_lower_bound(C, b), exact_lower_bound(C, b + 1)
+            # cells of the keys: floor(U m / 2^64), exact in rationals
+            ga = math.floor(Fraction(Ua, TWO64) * m)
+            gb = math.floor(Fraction(Ub, TWO64) * m)
+            if ga != gb:
+                assert lvl[b] == SENT, (b, m)
+                continue
+            sa, sb = format(Ua, "064b"), format(Ub, "064b")
+            diff = [k for k in range(64) if sa[k] != sb[k]]
+            assert lvl[b] == (64 - diff[0] if diff else 0), (b, m, sa, sb)
+
+
 # --------------------------------------------------------------------------
 # Fig. results_sine64: monotonic mapping of a regular grid (Sec. 2.6)
 # --------------------------------------------------------------------------
@@ -401,6 +462,9 @@ def test_quantize_properties(orc):
     # exact power-of-two scaling of the input does not change the result
     q2, _ = orc.quantize(v * np.float32(0.25))
     assert np.array_equal(q, q2)
+    # -0.0 is a zero weight: it neither sets the maximum nor gets mass
+    qz, sz = orc.quantize(np.array([-0.0, 0.5, -0.0, 0.25], np.float32))
+    assert qz.tolist() == [0, 2 ** 32 - 1, 0, 2 ** 31] and sz[0] == (2 ** 32 - 1) / 0.5
     tiny = np.array([1e-30, 1.0], np.float32)
     assert orc.quantize(tiny)[0].tolist() == [1, 2 ** 32 - 1]
     with pytest.raises(orc.OracleError):
