@@ -195,15 +195,50 @@ def load_stats(loads):
             "avg64": group(64)}
 
 
-def timed(fn, start, stop, reps):
+def timed(fn, start, stop, reps, before=None):
+    """Median and all times (ms) of fn() over reps runs, each bracketed by HIP
+    events on the current stream (the stream the library launches on);
+    before(), if given, runs ahead of each bracket (e.g. a cache flush)."""
     ts = []
     for _ in range(reps):
+        if before is not None:
+            before()
         start.record()
         fn()
         stop.record()
         stop.synchronize()
         ts.append(start.elapsed_time(stop))
-    return float(np.mean(ts)), ts
+    return float(np.median(ts)), ts
+
+
+def probe_lib():
+    """librtf_probe.so: the sampling step's memory pattern without a search."""
+    import ctypes
+    import importlib
+    bmod = importlib.import_module("paper_1901_05423_amd.build")
+    P = ctypes.CDLL(bmod.PROBE_LIB)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    P.rtf_probe_gather.argtypes = [vp, i64, vp, i64, vp, i64, i32, vp, vp, vp]
+    P.rtf_probe_gather.restype = ctypes.c_int
+    return P
+
+
+def host_cpu():
+    """Host CPU model and the cores this process may use."""
+    model = ""
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, usable
 
 
 def main():
@@ -215,6 +250,7 @@ def main():
     if args.config != "h24":
         {"c3": run_c3, "c4": run_c4, "c5": run_c5, "table1": run_table1}[args.config](args)
         return
+    import ctypes
     import torch
     import paper_1901_05423_amd as rtf
     from paper_1901_05423_amd import workloads as wl
@@ -241,7 +277,6 @@ def main():
     m = max(1, int(round(ratio * n)))
     idx = torch.empty(S, dtype=torch.int32, device=dev)
     x = torch.empty(S, dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
     holder = {}
 
     ws = torch.empty(rtf.lib().rtf_workspace_bytes(n, m), dtype=torch.uint8, device=dev)
@@ -269,20 +304,53 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = ev[0].elapsed_time(ev[1]) / args.steps
 
-    # per-phase times (each its own launch sequence, events on the same stream)
+    # per-phase times: medians of separately bracketed launch sequences, HIP
+    # events on the library's stream; warm (back to back) and cold (the
+    # 256 MB Infinity Cache flushed by a 512 MiB write before each repetition)
     f = holder["f"]
-    reps = max(3, args.steps)
+    reps = 5 if args.profile else max(50, args.steps)
     t_quant, _ = timed(lambda: rtf.quantize(v, out=(q, scale)), ev[2], ev[3], reps)
     t_build, _ = timed(lambda: rtf.build(q, m, ws=ws), ev[2], ev[3], reps)
     t_sample, _ = timed(lambda: rtf.sample(f, u, out=(idx, x)), ev[2], ev[3], reps)
     out = {}
     if not args.profile:
-        t_bs, _ = timed(lambda: rtf.sample_bsearch(f, u, out=(idx, x)), ev[2], ev[3], reps)
-        t_cb, _ = timed(lambda: rtf.sample_cutpoint_bsearch(f, u, out=(idx, x)), ev[2], ev[3],
-                        reps)
-        rtf.sample(f, u, out=(idx, x))
+        flush_buf = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        flush = lambda: flush_buf.fill_(7)  # noqa: E731
+        t_build_cold, _ = timed(lambda: rtf.build(q, m, ws=ws), ev[2], ev[3], reps, flush)
+        t_sample_cold, _ = timed(lambda: rtf.sample(f, u, out=(idx, x)), ev[2], ev[3], reps,
+                                 flush)
+        ref_idx = idx.clone()
+        # the same-GPU baselines; their indices must equal the forest's
+        idx_b = torch.empty_like(idx)
+        x_b = torch.empty_like(x)
+        t_bs, _ = timed(lambda: rtf.sample_bsearch(f, u, out=(idx_b, x_b)), ev[2], ev[3], 10)
+        assert torch.equal(idx_b, ref_idx), "binary search and forest indices differ"
+        t_cb, _ = timed(lambda: rtf.sample_cutpoint_bsearch(f, u, out=(idx_b, x_b)), ev[2], ev[3],
+                        10)
+        assert torch.equal(idx_b, ref_idx), "Cutpoint + bisection and forest indices differ"
         out["bsearch_samples_s"] = S / (t_bs * 1e-3)
         out["cutpoint_bsearch_samples_s"] = S / (t_cb * 1e-3)
+        # coherent uniforms: the same uniforms sorted, so that neighbouring
+        # lanes read neighbouring records (streaming instead of random lines)
+        sign = torch.tensor(-(1 << 63), dtype=torch.int64, device=dev)
+        u_sorted = (torch.sort(u.view(torch.int64) ^ sign).values ^ sign).view(u.dtype)
+        t_sorted, _ = timed(lambda: rtf.sample(f, u_sorted, out=(idx_b, x_b)), ev[2], ev[3], reps)
+        del u_sorted
+        # the same memory pattern without the search: one random 64-byte
+        # record per sample (and one more 16-byte node read for depth 2)
+        P = probe_lib()
+        pp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+        def gather(depth):
+            rc = P.rtf_probe_gather(ctypes.c_void_p(f.desc.cells), m,
+                                    ctypes.c_void_p(f.desc.nodes), n, pp(u), S, depth,
+                                    pp(idx_b), pp(x_b), st)
+            assert rc == 0, rc
+        t_g1, _ = timed(lambda: gather(1), ev[2], ev[3], reps)
+        t_g2, _ = timed(lambda: gather(2), ev[2], ev[3], reps)
+        t_g1_cold, _ = timed(lambda: gather(1), ev[2], ev[3], reps, flush)
+        del flush_buf
     if args.profile:
         # calibration for the HBM byte counters: a plain copy of known size
         src = torch.empty(1 << 28, dtype=torch.uint8, device=dev).fill_(1)
@@ -301,8 +369,15 @@ def main():
     per_sample = streams + LINE_B * loads  # what the memory system moves
     useful = streams + extra               # the bytes the search uses
     sample_bytes = per_sample * S
-    build_bytes = (W_B + NODE_B) * n + CELL_B * m
+    # build bytes as the method defines them: read w (4 B), write the key (8 B)
+    # and the two child references (8 B) per element, one 4-byte guide entry
+    # per cell
+    build_alg_bytes = (W_B + 8 + 8) * n + 4 * m
+    # what this design reads and writes: the weights twice (tile sums, then
+    # the tile kernel), 16-byte node records, 64-byte cell records
+    build_design_bytes = (2 * W_B + NODE_B) * n + CELL_B * m
     achieved = sample_bytes / (t_sample * 1e-3) / 1e9
+    build_gbs = build_alg_bytes / (t_build * 1e-3) / 1e9
     result = {
         "metric": METRIC,
         "value": S / (ms_step * 1e-3),
@@ -323,15 +398,18 @@ def main():
                         f"S=2^{args.log2s} u64 uniforms -> int32 index + f64 position",
             "n": n, "m": m, "samples": S, "cell_ratio": ratio, "cell_ratio_tuning": tune_info,
         },
-        "phase_ms": {"quantize": t_quant, "build": t_build, "sample": t_sample},
+        "phase_ms": {"quantize": t_quant, "build": t_build, "sample": t_sample,
+                     "statistic": f"median of {reps}"},
         "build_melem_s": n / (t_build * 1e-3) / 1e6,
-        "build_hbm_frac": build_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "sample_only_samples_s": S / (t_sample * 1e-3),
         "descent_nodes_when_needed": dbar,
         "resolved_by_cell_record": resolved,
         "roofline": {
             "kernel": "k_sample (Alg. 2 descent + position)",
             "bound": "hbm",
+            "counted_at": "L2 misses to the fabric: every random read moves a 128-byte line, and "
+                          "reads the 256 MB Infinity Cache serves count too (no counter here "
+                          "separates them from DRAM reads); cold-cache rate in sampling_cold",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -344,8 +422,43 @@ def main():
             "useful_bytes_per_sample": useful,
             "useful_frac": useful * S / (t_sample * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
+        "build_roofline": {
+            "kernels": "k_tile_sums + k_dist_params + k_build_tile + k_fixup",
+            "bound": "hbm",
+            "bytes_per_elem": build_alg_bytes / n,
+            "bytes_definition": "read w 4 B + write key 8 B + child0/child1 8 B per element, "
+                                "guide entry 4 B per cell",
+            "achieved": build_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": build_gbs / HBM_PEAK_GBS,
+            "design_bytes_per_elem": build_design_bytes / n,
+            "design_frac": build_design_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "design_bytes_definition": "w read twice, 16-byte node records, 64-byte cell records",
+        },
         "wall_s_timed": wall,
     }
+    if not args.profile:
+        cold_gbs = sample_bytes / (t_sample_cold * 1e-3) / 1e9
+        result["sampling_cold"] = {
+            "ms": t_sample_cold, "samples_s": S / (t_sample_cold * 1e-3),
+            "achieved_gbs": cold_gbs, "frac": cold_gbs / HBM_PEAK_GBS,
+            "flush": "512 MiB written before each repetition", "statistic": f"median of {reps}"}
+        result["build_cold"] = {
+            "ms": t_build_cold, "melem_s": n / (t_build_cold * 1e-3) / 1e6,
+            "frac": build_alg_bytes / (t_build_cold * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        result["sampling_sorted_u"] = {
+            "ms": t_sorted, "samples_s": S / (t_sorted * 1e-3),
+            "note": "the same uniforms in ascending order (coherent lanes)"}
+        result["gather_ceiling"] = {
+            "probe": "librtf_probe.so: stream u, read the 64-byte record floor(u m / 2^64) of the "
+                     "same guide table, write idx and x; depth 2 adds one dependent 16-byte read "
+                     "of the node array",
+            "depth1_samples_s": S / (t_g1 * 1e-3), "depth2_samples_s": S / (t_g2 * 1e-3),
+            "depth1_cold_samples_s": S / (t_g1_cold * 1e-3),
+            "sample_vs_depth1": t_g1 / t_sample,
+            "sample_cold_vs_depth1_cold": t_g1_cold / t_sample_cold,
+        }
     result.update(out)
 
     if not args.no_cpu and not args.profile:
@@ -354,31 +467,53 @@ def main():
 
 
 def cpu_baseline(v_h, u_h, n, m):
-    """The CPU oracle as it stands (single thread): quantise, prefix sum and
-    binary search with x on a bounded subsample of the uniforms."""
+    """The CPU oracle as it stands, timed on this host: quantise and prefix sum
+    over all n weights (one thread, as the oracle is serial), then binary
+    search with x on a bounded prefix of the uniforms, once on one thread and
+    once split into disjoint slices over the usable cores (one thread per
+    core, each calling the serial oracle; ctypes releases the GIL)."""
+    import threading
     import oracle
+    model, usable = host_cpu()
+    threads = max(1, min(usable, 16))
     t0 = time.perf_counter()
     q, _ = oracle.quantize(v_h)
     C = oracle.prefix(q)
     t_setup = time.perf_counter() - t0
-    k = 1 << 22
-    us = u_h[:k]
-    t0 = time.perf_counter()
-    oracle.search(q, us, C=C)
-    t_search = time.perf_counter() - t0
     S = u_h.size
-    total = t_setup + t_search * (S / k)
+    k1 = min(S, 1 << 22)
+    t0 = time.perf_counter()
+    oracle.search(q, u_h[:k1], C=C)
+    t_one = time.perf_counter() - t0
+    kN = min(S, k1 * threads)
+    bounds = np.linspace(0, kN, threads + 1).astype(np.int64)
+    work = [threading.Thread(target=oracle.search, args=(q, u_h[bounds[k]:bounds[k + 1]]),
+                             kwargs={"C": C}) for k in range(threads)]
+    t0 = time.perf_counter()
+    for th in work:
+        th.start()
+    for th in work:
+        th.join()
+    t_all = time.perf_counter() - t0
+    total_one = t_setup + t_one * (S / k1)
+    total_all = t_setup + t_all * (S / kN)
     t0 = time.perf_counter()
     oracle.forest(q, m=m)
     t_forest = time.perf_counter() - t0
     return {
-        "value": S / total,
+        "value": S / total_all,
         "unit": "samples/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"quantise + prefix over all n=2^{int(np.log2(n))} weights "
-                  f"({t_setup:.2f} s) plus binary search with x on the first 2^22 of the "
-                  f"2^{int(np.log2(S))} uniforms ({t_search:.2f} s), scaled to the full step",
+        "sample": f"quantise + prefix over all n=2^{int(np.log2(n))} weights on one thread "
+                  f"({t_setup:.2f} s), then binary search with x on the first {kN} of the "
+                  f"2^{int(np.log2(S))} uniforms split over {threads} threads ({t_all:.2f} s), "
+                  "scaled to the full step",
+        "host_cpu": model,
+        "usable_cores": usable,
+        "single_thread_samples_s": S / total_one,
+        "single_thread_sample": f"the same with the first {k1} uniforms on one thread "
+                                f"({t_one:.2f} s)",
         "oracle_forest_melem_s": n / t_forest / 1e6,
     }
 

@@ -11,6 +11,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtforest.so")
 SOURCES = ["rtf_abi.hip", "rtf_build.hip", "rtf_sample.hip", "rtf_quantize.hip",
            "rtf_backward.hip"]
+# measurement aid: the sampling kernels' memory pattern without the search
+PROBE_LIB = os.path.join(HERE, "librtf_probe.so")
+PROBE_SOURCES = ["rtf_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -23,15 +26,21 @@ FLAGS = [
 ]
 
 
-def build_library(verbose: bool = False) -> str:
-    """Build librtforest.so from csrc/*.hip; returns its path."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
+def _link(out: str, sources, verbose: bool) -> str:
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *[os.path.join(CSRC, s) for s in sources]]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build_library(verbose: bool = False) -> str:
+    """Build librtforest.so (and the measurement probe librtf_probe.so) from
+    csrc/*.hip; returns the path of librtforest.so."""
+    _link(PROBE_LIB, PROBE_SOURCES, verbose)
+    return _link(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":

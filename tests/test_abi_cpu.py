@@ -117,3 +117,30 @@ def test_fixed_point_helpers_exact(tmp_path):
                    capture_output=True)
     out = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0 and out.stdout.strip().endswith("OK"), out.stdout
+
+
+def test_probe_library_exports_its_header():
+    """The measurement probe (librtf_probe.so) exports what include/rtf_probe.h
+    declares and rejects bad arguments on the host."""
+    import importlib
+    b = importlib.import_module("paper_1901_05423_amd.build")
+    if not os.path.exists(b.PROBE_LIB):
+        b.build_library()
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "rtf_probe.h")).read(),
+                  flags=re.S)
+    names = sorted(set(re.findall(r"\b(rtf_[a-z0-9_]+)\s*\(", text)))
+    assert names == ["rtf_probe_gather"]
+    nm = subprocess.run(["nm", "-D", "--defined-only", b.PROBE_LIB], capture_output=True,
+                        text=True, check=True).stdout
+    assert set(names) <= set(re.findall(r"\bT (rtf_\w+)", nm))
+    P = ctypes.CDLL(b.PROBE_LIB)
+    f = P.rtf_probe_gather
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    f.argtypes = [vp, i64, vp, i64, vp, i64, i32, vp, vp, vp]
+    f.restype = ctypes.c_int
+    good = ctypes.c_void_p(256)
+    assert f(None, 1, None, 0, good, 1, 1, good, None, None) == 1  # no table
+    assert f(good, 0, None, 0, good, 1, 1, good, None, None) == 1  # m < 1
+    assert f(good, 1, None, 0, good, 1, 2, good, None, None) == 1  # depth 2 without nodes
+    assert f(ctypes.c_void_p(260), 1, None, 0, good, 1, 1, good, None, None) == 1  # misaligned
+    assert f(good, 1, None, 0, good, 0, 1, good, None, None) == 0  # nothing to do
