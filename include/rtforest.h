@@ -100,6 +100,7 @@ typedef struct rtf_forest {
     uint32_t *status;   /* device: status word (bit set per rtf_status code) */
     void *scratch;      /* device: build scratch */
     size_t scratch_bytes;
+    void *wide;         /* device: collapsed nodes (rtf_forest_widen), or NULL */
 } rtf_forest;
 
 /* ---- workspace sizing ------------------------------------------------- */
@@ -149,6 +150,32 @@ rtf_status rtf_build_batched(const uint32_t *w, const int64_t *elem_off,
                              int64_t n_total, int64_t m_total, void *ws,
                              size_t ws_bytes, hipStream_t stream,
                              rtf_forest *out);
+
+/* ---- collapsed nodes (Sec. 2.4 k-ary trees; Sec. 5) --------------------- */
+
+/* Bytes of workspace for rtf_forest_widen of a forest with n_total nodes;
+ * 0 if out of range. */
+size_t rtf_wide_workspace_bytes(int64_t n_total);
+
+/*
+ * Collapse two binary levels of the descended trees into one 64-byte record
+ * (a 4-ary tree, Sec. 5; memory transfer granularity, Sec. 2.4), so that a
+ * sample past its cell record reads one record per two levels.  Records are
+ * written for the internal nodes of every cell holding more than five lower
+ * bounds (the cells whose samples descend), at the node's index:
+ *   { uint64 k = U_j; uint64 kc[2]; int32 r[4]; 16 bytes unused }
+ * For child c of node j on side s (0: u < U_j, 1: u >= U_j): when c is a node,
+ * kc[s] = U_c and r[2s], r[2s+1] are c's children; when c is leaf ~i,
+ * r[2s] = r[2s+1] = c and kc[s] = 0.
+ *   f        a built forest (rtf_build / rtf_build_batched); on success its
+ *            `wide` field points at ws and every later sampling call on f
+ *            descends the collapsed records (same indices and positions)
+ *   ws       rtf_wide_workspace_bytes(f->n_total) bytes, 256-byte aligned,
+ *            owned by the caller; it must outlive the forest's use
+ * Asynchronous on the stream, after the build in stream order.  A rebuild
+ * into f's workspace clears f->wide (call rtf_forest_widen again).
+ */
+rtf_status rtf_forest_widen(rtf_forest *f, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- sampling (Alg. 2, Sec. 5) ---------------------------------------- */
 
@@ -248,6 +275,21 @@ rtf_status rtf_check(const rtf_forest *f, hipStream_t stream);
  * distributions' total weights. */
 rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, void *h_cells,
                              uint64_t *h_W, hipStream_t stream);
+
+/*
+ * The deepest search of the forest, counted as Alg. 2 counts memory reads:
+ * the guide entry plus the nodes visited down to the leaf, maximised over
+ * every uniform (over the leaves with positive weight, each from the cell
+ * holding its lower bound).  Written to the forest's status block and to
+ * *h_depth (host); synchronises the stream.  One distribution's bound: the
+ * keys of a cell differ below bit 65 - floor(log2 m) and the levels fall
+ * strictly along a path through distinct keys, while a run of zero weights
+ * (equal keys) is left at its first node, so the depth never exceeds
+ * 68 - floor(log2 m) whatever the weights -- the degenerate O(n) trees of
+ * Sec. 3 cannot be reached by a search here (the chains that zero runs form
+ * exist but no uniform descends them).
+ */
+rtf_status rtf_forest_depth(const rtf_forest *f, int32_t *h_depth, hipStream_t stream);
 
 /* Static string naming a status code. */
 const char *rtf_status_string(rtf_status s);

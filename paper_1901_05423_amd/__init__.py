@@ -52,6 +52,7 @@ class rtf_forest(ctypes.Structure):
         ("status", ctypes.c_void_p),
         ("scratch", ctypes.c_void_p),
         ("scratch_bytes", ctypes.c_size_t),
+        ("wide", ctypes.c_void_p),
     ]
 
 
@@ -65,6 +66,8 @@ SIGNATURES = {
     "rtf_workspace_bytes_batched": (_SZ, [_I32, _I64, _I64]),
     "rtf_build": (ctypes.c_int, [_P, _I64, _I64, _P, _SZ, _P, _FP]),
     "rtf_build_batched": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I64, _P, _SZ, _P, _FP]),
+    "rtf_wide_workspace_bytes": (_SZ, [_I64]),
+    "rtf_forest_widen": (ctypes.c_int, [_FP, _P, _SZ, _P]),
     "rtf_sample": (ctypes.c_int, [_FP, _P, _I64, _P, _P, _P]),
     "rtf_sample_batched": (ctypes.c_int, [_FP, _P, _P, _I64, _P, _P, _P]),
     "rtf_sample_2d": (ctypes.c_int, [_FP, _P, _I64, _P, _P, _P]),
@@ -74,6 +77,7 @@ SIGNATURES = {
     "rtf_backward_workspace_bytes": (_SZ, [_I32, _I64]),
     "rtf_backward": (ctypes.c_int, [_FP, _P, _P, _P, _P, _I64, _P, _P, _P, _SZ, _P]),
     "rtf_check": (ctypes.c_int, [_FP, _P]),
+    "rtf_forest_depth": (ctypes.c_int, [_FP, _P, _P]),
     "rtf_forest_export": (ctypes.c_int, [_FP, _P, _P, _P, _P]),
     "rtf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -146,6 +150,35 @@ class Forest:
     @property
     def m_total(self):
         return self.desc.m_total
+
+    def widen(self, ws=None, stream=None):
+        """Collapsed 4-ary records for the descended cells (rtf_forest_widen);
+        later sampling calls on this forest read them.  Returns self."""
+        nb = lib().rtf_wide_workspace_bytes(self.n_total)
+        if nb == 0:
+            raise RtfError(RTF_ERR_SIZE, "rtf_wide_workspace_bytes")
+        if ws is None or ws.numel() < nb:
+            ws = _workspace(nb, self.device)
+        _check(lib().rtf_forest_widen(ctypes.byref(self.desc), _ptr(ws), nb, _stream(stream)),
+               "rtf_forest_widen")
+        self.wide_ws = ws
+        return self
+
+    def wide_view(self):
+        """Device view of the collapsed records: int64 [n_total, 8] (k, kc0,
+        kc1, r0|r1, r2|r3, unused x3), or None before widen()."""
+        if getattr(self, "wide_ws", None) is None or not self.desc.wide:
+            return None
+        torch = _torch()
+        return self.wide_ws[:64 * self.n_total].view(torch.int64).view(self.n_total, 8)
+
+    def depth(self, stream=None) -> int:
+        """The deepest search (guide entry + nodes, as Alg. 2 counts reads)
+        any uniform makes in this forest (rtf_forest_depth); synchronises."""
+        d = ctypes.c_int32(0)
+        _check(lib().rtf_forest_depth(ctypes.byref(self.desc), ctypes.byref(d), _stream(stream)),
+               "rtf_forest_depth")
+        return int(d.value)
 
     def check(self, stream=None):
         """Synchronise and raise on a device-detected data error."""

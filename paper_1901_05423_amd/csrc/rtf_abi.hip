@@ -130,6 +130,32 @@ bool sample_args_ok(const uint64_t *u, int64_t S, const int32_t *idx, const doub
     return u && idx && aligned(u, 8) && aligned(idx, 4) && (!x || aligned(x, 8));
 }
 
+// Backward scratch layout: B[n], D[n], A[D], head[nch], carry[nch], link[nch].
+size_t backward_layout(int32_t D, int64_t n, char *base, BackwardScratch *w) {
+    const int64_t nch = backward_chunks(n);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return base + at;
+    };
+    char *B = take(sizeof(double) * (size_t)n);
+    char *Dv = take(sizeof(double) * (size_t)n);
+    char *A = take(sizeof(double) * (size_t)D);
+    char *head = take(sizeof(double) * (size_t)nch);
+    char *carry = take(sizeof(double) * (size_t)nch);
+    char *link = take(sizeof(int32_t) * (size_t)nch);
+    if (w) {
+        w->B = reinterpret_cast<double *>(B);
+        w->Dv = reinterpret_cast<double *>(Dv);
+        w->A = reinterpret_cast<double *>(A);
+        w->head = reinterpret_cast<double *>(head);
+        w->carry = reinterpret_cast<double *>(carry);
+        w->link = reinterpret_cast<int32_t *>(link);
+    }
+    return o;
+}
+
 }  // namespace
 
 extern "C" {
@@ -160,11 +186,45 @@ rtf_status rtf_build_batched(const uint32_t *w, const int64_t *elem_off, const i
     return build_common(w, elem_off, cell_off, D, n_total, m_total, ws, ws_bytes, stream, out);
 }
 
+size_t rtf_wide_workspace_bytes(int64_t n_total) {
+    if (n_total < 1 || n_total > MAX_I32) return 0;
+    return align256(sizeof(Wide) * (size_t)n_total);
+}
+
+rtf_status rtf_forest_widen(rtf_forest *f, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (!forest_ok(f) || !ws || !aligned(ws, 256)) return RTF_ERR_INVALID_ARG;
+    if (ws_bytes < rtf_wide_workspace_bytes(f->n_total)) return RTF_ERR_WORKSPACE;
+    Wide *w = static_cast<Wide *>(ws);
+    const hipError_t e = launch_widen(static_cast<const Node *>(f->nodes),
+                                      static_cast<const Cell *>(f->cells),
+                                      static_cast<const Dist *>(f->dists), f->elem_off, f->D,
+                                      f->n_total, w, stream);
+    if (e != hipSuccess) return RTF_ERR_HIP;
+    f->wide = ws;
+    return RTF_OK;
+}
+
+rtf_status rtf_forest_depth(const rtf_forest *f, int32_t *h_depth, hipStream_t stream) {
+    if (!forest_ok(f) || !h_depth) return RTF_ERR_INVALID_ARG;
+    uint32_t *word = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(f->status) +
+                                                  STATUS_DEPTH_OFFSET);
+    if (launch_depth(static_cast<const Node *>(f->nodes), static_cast<const Cell *>(f->cells),
+                     static_cast<const Dist *>(f->dists), f->elem_off, f->D, f->n_total, word,
+                     stream) != hipSuccess)
+        return RTF_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RTF_ERR_HIP;
+    uint32_t v = 0;
+    if (hipMemcpy(&v, word, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return RTF_ERR_HIP;
+    *h_depth = (int32_t)v;
+    return RTF_OK;
+}
+
 rtf_status rtf_sample(const rtf_forest *f, const uint64_t *u, int64_t S, int32_t *out_idx,
                       double *out_x, hipStream_t stream) {
     if (!forest_ok(f) || !sample_args_ok(u, S, out_idx, out_x)) return RTF_ERR_INVALID_ARG;
     if (S == 0) return RTF_OK;
     return from_hip(launch_sample(static_cast<const Node *>(f->nodes),
+                                  static_cast<const Wide *>(f->wide),
                                   static_cast<const Cell *>(f->cells),
                                   static_cast<const Dist *>(f->dists), nullptr, 1, f->n_total, f->m_total, u, S,
                                   out_idx, out_x, stream));
@@ -176,6 +236,7 @@ rtf_status rtf_sample_batched(const rtf_forest *f, const int64_t *sample_off, co
     if (!sample_off || !aligned(sample_off, 8)) return RTF_ERR_INVALID_ARG;
     if (S == 0) return RTF_OK;
     return from_hip(launch_sample(static_cast<const Node *>(f->nodes),
+                                  static_cast<const Wide *>(f->wide),
                                   static_cast<const Cell *>(f->cells),
                                   static_cast<const Dist *>(f->dists), sample_off, f->D, f->n_total,
                                   f->m_total, u, S, out_idx, out_x, stream));
@@ -190,7 +251,8 @@ rtf_status rtf_sample_2d(const rtf_forest *f, const uint64_t *u2, int64_t S, int
         return RTF_ERR_INVALID_ARG;
     if (S == 0) return RTF_OK;
     return from_hip(launch_sample_2d(static_cast<const Node *>(f->nodes),
-                                  static_cast<const Cell *>(f->cells),
+                                     static_cast<const Wide *>(f->wide),
+                                     static_cast<const Cell *>(f->cells),
                                      static_cast<const Dist *>(f->dists), f->D, f->n_total, u2, S,
                                      out_rc, out_xy, stream));
 }
@@ -230,7 +292,7 @@ rtf_status rtf_quantize_f32(const float *v, const int64_t *elem_off, int32_t D, 
 
 size_t rtf_backward_workspace_bytes(int32_t D, int64_t n_total) {
     if (D < 1 || n_total < D || n_total > MAX_I32) return 0;
-    return align256(sizeof(double) * (size_t)n_total) * 2 + align256(sizeof(double) * (size_t)D);
+    return backward_layout(D, n_total, nullptr, nullptr);
 }
 
 rtf_status rtf_backward(const rtf_forest *f, const int64_t *sample_off, const uint64_t *u,
@@ -242,14 +304,12 @@ rtf_status rtf_backward(const rtf_forest *f, const int64_t *sample_off, const ui
     if (!aligned(ws, 256) || !aligned(grad_w, 8) || !aligned(scale, 8))
         return RTF_ERR_INVALID_ARG;
     if (ws_bytes < rtf_backward_workspace_bytes(f->D, f->n_total)) return RTF_ERR_WORKSPACE;
-    char *b = static_cast<char *>(ws);
-    double *B = reinterpret_cast<double *>(b);
-    double *Dv = reinterpret_cast<double *>(b + align256(sizeof(double) * (size_t)f->n_total));
-    double *A = reinterpret_cast<double *>(b + 2 * align256(sizeof(double) * (size_t)f->n_total));
+    BackwardScratch w;
+    backward_layout(f->D, f->n_total, static_cast<char *>(ws), &w);
     return from_hip(launch_backward(static_cast<const Node *>(f->nodes),
-                                    static_cast<const Dist *>(f->dists), f->D, f->n_total,
-                                    f->D > 1 ? sample_off : nullptr, u, idx, grad_x, S, scale,
-                                    grad_w, B, Dv, A, stream));
+                                    static_cast<const Dist *>(f->dists), f->elem_off, f->D,
+                                    f->n_total, f->D > 1 ? sample_off : nullptr, u, idx, grad_x,
+                                    S, scale, grad_w, w, stream));
 }
 
 rtf_status rtf_check(const rtf_forest *f, hipStream_t stream) {

@@ -8,8 +8,8 @@
 // and with a_s = g_s / (n_d w_{i_s}):
 //   dL/dv_k = A_d - sum_{j > k} B_j - D_k,
 //   A_d = sum_s a_s xi_s,  B_j = sum_{i_s = j} a_s,  D_j = sum_{i_s = j} a_s frac_s.
-// k_bscatter accumulates A, B, D; k_bcombine does the segmented suffix sum of
-// B per distribution.  A block whose samples all belong to one distribution
+// k_bscatter accumulates A, B, D; k_bhead, k_bcarry and k_bfinal do the
+// suffix sum of B segmented by distribution.  A block whose samples all belong to one distribution
 // of at most LBINS elements sums B and D in LDS first and adds each bin to
 // global memory once; otherwise every sample adds with FP64 global atomics.
 #include "rtf_internal.h"
@@ -246,67 +246,235 @@ __global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void k_
     }
 }
 
-// One block per distribution: grad[k] = A - sum_{j>k} B_j - D_k, scanning the
-// distribution from its end in chunks of CB elements.
-__global__ __launch_bounds__(CB) void k_bcombine(const Dist *__restrict__ dists,
-                                                 const double *__restrict__ B,
-                                                 const double *__restrict__ Dv,
-                                                 const double *__restrict__ A,
-                                                 double *__restrict__ grad) {
-    __shared__ double s_w[CB / 64];
-    const Dist P = dists[blockIdx.x];
-    const double Ad = A[blockIdx.x];
+// ---------------------------------------------------------------------------
+// The combining pass: grad[k] = A_d - sum_{j > k, j in d} B_j - D_k, a suffix
+// sum of B segmented by distribution, over the whole element range so that
+// one large distribution spreads over the whole GPU.  The elements are cut
+// into chunks of CCH; a chunk's own part of the suffix sum is a block-wide
+// segmented scan, and the part from later chunks is a carry per chunk:
+//   k_bhead    per chunk: the sum of B over its elements that belong to the
+//              distribution of its first element, and whether the
+//              distribution of its last element continues past it;
+//   k_bcarry   one block: carry[c] = sum of B over the elements after chunk c
+//              of the distribution of its last element, a segmented suffix
+//              scan over the chunks;
+//   k_bfinal   per chunk: the in-chunk segmented suffix scan plus the carry.
+// ---------------------------------------------------------------------------
+constexpr int CE = 4;           // elements per thread of a chunk
+constexpr int CCH = CB * CE;    // elements per chunk
+static_assert(CCH == BACKWARD_CHUNK, "chunk of the combining pass");
+constexpr int CARRY_PER = 4;    // chunks per thread and round of k_bcarry
+
+// One term of a segmented sum: f marks that a segment starts at this term
+// (so nothing before it is added).  join(a, b), a before b in scan order.
+struct SegSum {
+    double v;
+    int f;
+};
+__device__ inline SegSum seg_join(SegSum a, SegSum b) {
+    SegSum r;
+    r.v = b.f ? b.v : a.v + b.v;
+    r.f = a.f | b.f;
+    return r;
+}
+
+// Block-wide segmented scan in thread order: returns the join of the terms
+// of all threads before this one (the identity {0, 0} for thread 0) and, in
+// total, the join of all threads' terms.
+template <int NT>
+__device__ inline SegSum block_seg_excl(SegSum x, double *s_v, int *s_f, SegSum &total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double carry = 0.0;  // sum of B over elements after the current chunk
-    for (int64_t end = P.eo + P.n; end > P.eo; end -= CB) {
-        // element handled by this thread: end-1-threadIdx.x (reverse order)
-        const int64_t k = end - 1 - threadIdx.x;
-        const bool ok = k >= P.eo;
-        const double b = ok ? B[k] : 0.0;
-        // inclusive scan over threads in reverse element order
-        double x = b;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            double y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) s_w[w] = x;
-        __syncthreads();
-        double off = 0.0, tot = 0.0;
+    for (int o = 1; o < 64; o <<= 1) {
+        SegSum y;
+        y.v = __shfl_up(x.v, o, 64);
+        y.f = __shfl_up(x.f, o, 64);
+        if (lane >= o) x = seg_join(y, x);
+    }
+    if (lane == 63) {
+        s_v[w] = x.v;
+        s_f[w] = x.f;
+    }
+    SegSum prev;
+    prev.v = __shfl_up(x.v, 1, 64);
+    prev.f = __shfl_up(x.f, 1, 64);
+    if (lane == 0) prev = SegSum{0.0, 0};
+    __syncthreads();
+    SegSum pre{0.0, 0}, tot{0.0, 0};
 #pragma unroll
-        for (int i = 0; i < CB / 64; ++i) {
-            off += (i < w) ? s_w[i] : 0.0;
-            tot += s_w[i];
+    for (int i = 0; i < NT / 64; ++i) {
+        const SegSum t{s_v[i], s_f[i]};
+        if (i < w) pre = seg_join(pre, t);
+        tot = seg_join(tot, t);
+    }
+    __syncthreads();
+    total = tot;
+    return seg_join(pre, prev);
+}
+
+// The distribution of the first and the last element of chunk [c0, c1), by
+// two wave-wide searches (waves 0 and 1); valid in every thread.
+__device__ inline void chunk_dists(const int64_t *eoff, int32_t D, int64_t c0, int64_t c1,
+                                   int32_t *s_d, int32_t &dfirst, int32_t &dlast) {
+    if (D == 1) {
+        dfirst = dlast = 0;
+        return;
+    }
+    const int w = threadIdx.x >> 6;
+    if (w < 2) {
+        const int32_t d = wave_upper_bound(eoff, D, w == 0 ? c0 : c1 - 1) - 1;
+        if ((threadIdx.x & 63) == 0) s_d[w] = d;
+    }
+    __syncthreads();
+    dfirst = s_d[0];
+    dlast = s_d[1];
+}
+
+// head[c]: sum of B over chunk c's elements in the distribution of its first
+// element; link[c]: bit 0 the chunk lies inside that distribution, bit 1 the
+// distribution of its last element continues into the next chunk.
+__global__ __launch_bounds__(CB) void k_bhead(const int64_t *__restrict__ eoff, int32_t D,
+                                              int64_t n, const double *__restrict__ B,
+                                              double *__restrict__ head, int32_t *__restrict__ link) {
+    __shared__ int32_t s_d[2];
+    __shared__ double s_red[CB / 64];
+    const int64_t c = blockIdx.x;
+    const int64_t c0 = c * CCH, c1 = c0 + CCH < n ? c0 + CCH : n;
+    int32_t dfirst, dlast;
+    chunk_dists(eoff, D, c0, c1, s_d, dfirst, dlast);
+    const int64_t e_first = eoff[dfirst + 1], e_last = eoff[dlast + 1];
+    const int64_t hend = e_first < c1 ? e_first : c1;
+    double x = 0.0;
+    for (int64_t k = c0 + threadIdx.x; k < hend; k += CB) x += B[k];
+    const double t = block_sum<CB>(x, s_red);
+    if (threadIdx.x == 0) {
+        head[c] = t;
+        link[c] = (e_first >= c1 ? 1 : 0) | (e_last > c1 ? 2 : 0);
+    }
+}
+
+// carry[c] = [chunk c's last distribution continues] * (head[c+1] +
+// [chunk c+1 lies inside it] * carry[c+1]): a segmented scan from the last
+// chunk down, CB * CARRY_PER chunks per round, one block.
+__global__ __launch_bounds__(CB) void k_bcarry(const double *__restrict__ head,
+                                               const int32_t *__restrict__ link, int64_t nch,
+                                               double *__restrict__ carry) {
+    __shared__ double s_v[CB / 64];
+    __shared__ int s_f[CB / 64];
+    double carry_in = 0.0;  // carry of the chunk after the round
+    for (int64_t top = nch - 1; top >= 0; top -= (int64_t)CB * CARRY_PER) {
+        // thread T takes chunks top - CARRY_PER T - e, e = 0 .. CARRY_PER-1
+        SegSum term[CARRY_PER], agg{0.0, 0};
+#pragma unroll
+        for (int e = 0; e < CARRY_PER; ++e) {
+            const int64_t c = top - (int64_t)CARRY_PER * threadIdx.x - e;
+            term[e] = SegSum{0.0, 1};
+            if (c >= 0 && c + 1 < nch) {
+                const int32_t lc = link[c];
+                const bool cont = lc & 2;
+                const bool through = cont && (link[c + 1] & 1);
+                term[e] = SegSum{cont ? head[c + 1] : 0.0, through ? 0 : 1};
+            }
+            agg = seg_join(agg, term[e]);
         }
-        __syncthreads();
-        // exclusive sum of B over elements right of k
-        const double right = carry + off + x - b;
-        if (ok) grad[k] = Ad - right - Dv[k];
-        carry += tot;
+        SegSum total;
+        SegSum run = block_seg_excl<CB>(agg, s_v, s_f, total);
+#pragma unroll
+        for (int e = 0; e < CARRY_PER; ++e) {
+            const int64_t c = top - (int64_t)CARRY_PER * threadIdx.x - e;
+            run = seg_join(run, term[e]);
+            if (c >= 0) carry[c] = run.v + (run.f ? 0.0 : carry_in);
+        }
+        carry_in = total.v + (total.f ? 0.0 : carry_in);
+    }
+}
+
+// grad[k] = A_d - (the in-chunk suffix sum of B after k within d) - (carry of
+// the chunk when d continues past it) - D_k.  Thread T takes the elements
+// c1 - 1 - (CE T + e), e = 0 .. CE-1 (scan order is descending k); a term
+// starts a segment at the last element of its distribution.
+__global__ __launch_bounds__(CB) void k_bfinal(const int64_t *__restrict__ eoff, int32_t D,
+                                               int64_t n, const double *__restrict__ B,
+                                               const double *__restrict__ Dv,
+                                               const double *__restrict__ A,
+                                               const double *__restrict__ carry,
+                                               double *__restrict__ grad) {
+    __shared__ int64_t s_off[CCH + 1];
+    __shared__ int32_t s_d[2];
+    __shared__ double s_v[CB / 64];
+    __shared__ int s_f[CB / 64];
+    const int64_t c = blockIdx.x;
+    const int64_t c0 = c * CCH, c1 = c0 + CCH < n ? c0 + CCH : n;
+    int32_t dfirst, dlast;
+    chunk_dists(eoff, D, c0, c1, s_d, dfirst, dlast);
+    // the ends of the chunk's distributions: s_off[q] = eoff[dfirst + 1 + q]
+    const int32_t nd = dlast - dfirst + 1;  // <= CCH: every distribution holds an element
+    for (int32_t q = threadIdx.x; q < nd; q += CB) s_off[q] = eoff[dfirst + 1 + q];
+    __syncthreads();
+    const double cin = carry[c];
+    int64_t kk[CE];
+    int32_t dq[CE];
+    double b[CE];
+    SegSum term[CE], agg{0.0, 0};
+    // distribution of the thread's first (highest) element, then downwards
+    const int64_t ktop = c1 - 1 - (int64_t)CE * threadIdx.x;
+    int32_t lo = 0, hi = nd;  // first q with s_off[q] > ktop
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= ktop) lo = mid + 1;
+        else hi = mid;
+    }
+    int32_t q = lo < nd ? lo : nd - 1;
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        const int64_t k = ktop - e;
+        kk[e] = k;
+        const bool ok = k >= c0;
+        while (ok && q > 0 && s_off[q - 1] > k) --q;
+        dq[e] = q;
+        b[e] = ok ? B[k] : 0.0;
+        term[e] = SegSum{b[e], ok && s_off[q] == k + 1 ? 1 : 0};
+        agg = seg_join(agg, term[e]);
+    }
+    SegSum total;
+    SegSum run = block_seg_excl<CB>(agg, s_v, s_f, total);
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        run = seg_join(run, term[e]);
+        const int64_t k = kk[e];
+        if (k < c0) continue;
+        const int32_t d = dfirst + dq[e];
+        const double right = run.v - b[e] + (d == dlast ? cin : 0.0);
+        grad[k] = A[d] - right - Dv[k];
     }
 }
 
 }  // namespace
 
-hipError_t launch_backward(const Node *nodes, const Dist *dists, int32_t D, int64_t n_total,
-                           const int64_t *sample_off, const uint64_t *u, const int32_t *idx,
-                           const double *gx, int64_t S, const double *scale, double *grad_w,
-                           double *wsB, double *wsDv, double *wsA, hipStream_t st) {
+hipError_t launch_backward(const Node *nodes, const Dist *dists, const int64_t *elem_off,
+                           int32_t D, int64_t n_total, const int64_t *sample_off,
+                           const uint64_t *u, const int32_t *idx, const double *gx, int64_t S,
+                           const double *scale, double *grad_w, const BackwardScratch &w,
+                           hipStream_t st) {
     int64_t zb = (n_total + 255) / 256;
     if (zb > 4096) zb = 4096;
-    hipLaunchKernelGGL(k_bzero, dim3((unsigned)zb), dim3(256), 0, st, wsB, wsDv, n_total, wsA,
+    hipLaunchKernelGGL(k_bzero, dim3((unsigned)zb), dim3(256), 0, st, w.B, w.Dv, n_total, w.A,
                        D);
     if (S > 0) {
         const int64_t nb = (S + CHUNK - 1) / CHUNK;
         if (sample_off)
             hipLaunchKernelGGL(k_bscatter<true>, dim3((unsigned)nb), dim3(SB), 0, st, nodes, dists,
-                               D, sample_off, u, idx, gx, S, scale, wsB, wsDv, wsA);
+                               D, sample_off, u, idx, gx, S, scale, w.B, w.Dv, w.A);
         else
             hipLaunchKernelGGL(k_bscatter<false>, dim3((unsigned)nb), dim3(SB), 0, st, nodes, dists,
-                               D, sample_off, u, idx, gx, S, scale, wsB, wsDv, wsA);
+                               D, sample_off, u, idx, gx, S, scale, w.B, w.Dv, w.A);
     }
-    hipLaunchKernelGGL(k_bcombine, dim3((unsigned)D), dim3(CB), 0, st, dists, wsB, wsDv, wsA,
-                       grad_w);
+    const int64_t nch = backward_chunks(n_total);
+    hipLaunchKernelGGL(k_bhead, dim3((unsigned)nch), dim3(CB), 0, st, elem_off, D, n_total, w.B,
+                       w.head, w.link);
+    hipLaunchKernelGGL(k_bcarry, dim3(1), dim3(CB), 0, st, w.head, w.link, nch, w.carry);
+    hipLaunchKernelGGL(k_bfinal, dim3((unsigned)nch), dim3(CB), 0, st, elem_off, D, n_total, w.B,
+                       w.Dv, w.A, w.carry, grad_w);
     return hipGetLastError();
 }
 

@@ -260,29 +260,6 @@ __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// The first d in [0, D] with off[d] > i (D + 1 if none; off[0..D]
-// non-decreasing), found by one wave (uniform i): each step probes 64 evenly
-// spaced offsets and keeps the bracket between the last one at or below i
-// and the first above it.  Every lane of the wave must call it.
-__device__ inline int32_t wave_upper_bound(const int64_t *off, int32_t D, int64_t i) {
-    const int32_t lane = threadIdx.x & 63;
-    int32_t lo = 0, hi = D + 1;  // the answer lies in [lo, hi]
-    while (lo < hi) {
-        const int32_t step = (hi - lo + 63) / 64;
-        const int32_t p = lo + lane * step;
-        const int32_t cnt = __popcll(__ballot(p < hi && off[p] <= i));  // a prefix of the lanes
-        if (cnt == 0) {
-            hi = lo;
-        } else {
-            const int32_t last = lo + (cnt - 1) * step;  // off[last] <= i
-            const int32_t next = lo + cnt * step;       // off[next] > i, or next >= hi
-            lo = last + 1;
-            hi = next < hi ? next : hi;
-        }
-    }
-    return lo;
-}
-
 // k_tile_sums: the prefix-sum pass over the weights (Sec. 2.6 notes that the
 // prefix sum of an inversion method computes efficiently in parallel)
 // ---------------------------------------------------------------------------
@@ -1223,6 +1200,157 @@ __device__ void fixup_tile(const BuildArgs &a, int64_t t) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// k_widen: collapsed (4-ary) nodes for the cells whose trees samples descend
+// (Sec. 5: a wider tree results from collapsing two binary levels; on this
+// GPU every random read moves a whole line, so a 64-byte record holding two
+// levels costs the same read as a 16-byte one).  One thread per node j; the
+// record is written for the internal nodes of cells with more than
+// CELL_BOUNDS lower bounds (all but the cell's first node a, whose child 1
+// is where those samples' descent starts).
+// ---------------------------------------------------------------------------
+constexpr int WT = 256;
+
+template <bool BATCHED>
+__global__ __launch_bounds__(WT) void k_widen(const Node *__restrict__ nodes,
+                                              const Cell *__restrict__ cells,
+                                              const Dist *__restrict__ dists,
+                                              const int64_t *__restrict__ eoff, int32_t D,
+                                              int64_t n, Wide *__restrict__ wide) {
+    __shared__ int32_t s_d[2];
+    const int64_t j0 = (int64_t)blockIdx.x * WT;
+    const int64_t j = j0 + threadIdx.x;
+    int32_t dlo = 0, dhi = 0;
+    if (BATCHED) {
+        // distributions of the block's first and last node, one wave each
+        const int w = threadIdx.x >> 6;
+        if (w < 2) {
+            const int64_t jl = j0 + WT - 1 < n ? j0 + WT - 1 : n - 1;
+            const int32_t d = wave_upper_bound(eoff, D, w == 0 ? j0 : jl) - 1;
+            if ((threadIdx.x & 63) == 0) s_d[w] = d;
+        }
+        __syncthreads();
+        dlo = s_d[0];
+        dhi = s_d[1];
+    }
+    if (j >= n) return;
+    const Node nd = nodes[j];
+    if (nd.key == KEY_END) return;  // past the last positive weight: never descended
+    const int32_t d = (!BATCHED || dlo == dhi) ? dlo : find_segment_in(eoff, dlo, dhi + 1, j);
+    const Dist P = dists[d];
+    if (P.flags & DIST_ZERO) return;
+    const int64_t g = cell_of_key(nd.key, P);
+    const int2 ra = *reinterpret_cast<const int2 *>(&cells[g].ref);
+    if (ra.x < 0 || ra.y < 0 || ra.x == (int32_t)j) return;  // covered, resolved by its record, or node a
+    uint64_t kc[2];
+    int32_t r[4];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int32_t c = side ? nd.c1 : nd.c0;
+        if (c >= 0) {
+            const Node cn = nodes[c];
+            kc[side] = cn.key;
+            r[2 * side] = cn.c0;
+            r[2 * side + 1] = cn.c1;
+        } else {
+            kc[side] = 0;
+            r[2 * side] = r[2 * side + 1] = c;
+        }
+    }
+    uint4 *q = reinterpret_cast<uint4 *>(wide + j);
+    q[0] = make_uint4((uint32_t)nd.key, (uint32_t)(nd.key >> 32), (uint32_t)kc[0],
+                      (uint32_t)(kc[0] >> 32));
+    q[1] = make_uint4((uint32_t)kc[1], (uint32_t)(kc[1] >> 32), (uint32_t)r[0], (uint32_t)r[1]);
+    q[2] = make_uint4((uint32_t)r[2], (uint32_t)r[3], 0u, 0u);
+    q[3] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_widen(const Node *nodes, const Cell *cells, const Dist *dists,
+                        const int64_t *elem_off, int32_t D, int64_t n_total, Wide *wide,
+                        hipStream_t st) {
+    const dim3 g((unsigned)((n_total + WT - 1) / WT)), b(WT);
+    if (D > 1)
+        hipLaunchKernelGGL(k_widen<true>, g, b, 0, st, nodes, cells, dists, elem_off, D, n_total,
+                           wide);
+    else
+        hipLaunchKernelGGL(k_widen<false>, g, b, 0, st, nodes, cells, dists, elem_off, D, n_total,
+                           wide);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k_depth: the deepest search of the forest, counted as Alg. 2 counts it (the
+// guide entry, then one node per step).  Every u in leaf i's interval takes
+// the path that u = U_i takes from the cell holding U_i (the keys compared
+// lie outside the interval), and from a later cell the interval covers the
+// search ends at once (a covered cell) or after node a, whose child 0 is i.
+// So the maximum over the leaves with positive weight of the path for U_i
+// is the deepest search any uniform makes.  One thread per leaf; the result
+// goes to the forest's status block with an atomic maximum.
+// ---------------------------------------------------------------------------
+template <bool BATCHED>
+__global__ __launch_bounds__(WT) void k_depth(const Node *__restrict__ nodes,
+                                              const Cell *__restrict__ cells,
+                                              const Dist *__restrict__ dists,
+                                              const int64_t *__restrict__ eoff, int32_t D,
+                                              int64_t n, uint32_t *depth) {
+    __shared__ int32_t s_d[2];
+    const int64_t i0 = (int64_t)blockIdx.x * WT;
+    const int64_t i = i0 + threadIdx.x;
+    int32_t dlo = 0, dhi = 0;
+    if (BATCHED) {
+        const int w = threadIdx.x >> 6;
+        if (w < 2) {
+            const int64_t il = i0 + WT - 1 < n ? i0 + WT - 1 : n - 1;
+            const int32_t d = wave_upper_bound(eoff, D, w == 0 ? i0 : il) - 1;
+            if ((threadIdx.x & 63) == 0) s_d[w] = d;
+        }
+        __syncthreads();
+        dlo = s_d[0];
+        dhi = s_d[1];
+    }
+    uint32_t steps = 0;
+    if (i < n) {
+        const int32_t d = (!BATCHED || dlo == dhi) ? dlo : find_segment_in(eoff, dlo, dhi + 1, i);
+        const Dist P = dists[d];
+        const uint64_t key = nodes[i].key;
+        const uint64_t next = i + 1 < P.eo + P.n ? nodes[i + 1].key : KEY_END;
+        // leaf i carries mass: its key is real and the next bound lies above it
+        const bool live = !(P.flags & DIST_ZERO) && key != KEY_END && (next != key || next == KEY_END);
+        if (live) {
+            int32_t j = cells[cell_of_key(key, P)].ref;
+            steps = 1;  // the guide entry
+            for (int64_t guard = 0; j >= 0 && guard <= n; ++guard) {
+                const Node nd = nodes[j];
+                j = key < nd.key ? nd.c0 : nd.c1;
+                ++steps;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t y = __shfl_xor(steps, o, 64);
+        steps = y > steps ? y : steps;
+    }
+    if ((threadIdx.x & 63) == 0 && steps) atomicMax(depth, steps);
+}
+
+__global__ void k_clear_word(uint32_t *w) { *w = 0u; }
+
+hipError_t launch_depth(const Node *nodes, const Cell *cells, const Dist *dists,
+                        const int64_t *elem_off, int32_t D, int64_t n_total, uint32_t *depth,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(1), 0, st, depth);
+    const dim3 g((unsigned)((n_total + WT - 1) / WT)), b(WT);
+    if (D > 1)
+        hipLaunchKernelGGL(k_depth<true>, g, b, 0, st, nodes, cells, dists, elem_off, D, n_total,
+                           depth);
+    else
+        hipLaunchKernelGGL(k_depth<false>, g, b, 0, st, nodes, cells, dists, elem_off, D, n_total,
+                           depth);
+    return hipGetLastError();
+}
+
 hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
     const bool vec = (reinterpret_cast<uintptr_t>(a.w) & 15) == 0;
     const dim3 grid((unsigned)a.ntiles);

@@ -37,6 +37,20 @@ struct alignas(16) Node {
     int32_t c0, c1;
 };
 
+// Collapsed node (Sec. 5: a 4-ary tree from two binary levels), 64 bytes, one
+// per internal node j of a cell whose tree the samples descend (a cell with
+// more than CELL_BOUNDS lower bounds), stored at index j.  k = U_j; for its
+// child c on side s (0 left, 1 right): when c is a node, kc[s] = U_c and
+// r[2s], r[2s+1] are c's two children; when c is a leaf, r[2s] = r[2s+1] = c
+// and kc[s] = 0.  References as in Node (>= 0 node, < 0 leaf ~i).
+struct alignas(64) Wide {
+    uint64_t k;
+    uint64_t kc[2];
+    int32_t r[4];
+    uint64_t pad[2];
+};
+static_assert(sizeof(Wide) == 64, "collapsed nodes are 64 bytes");
+
 // Guide-table cell record, 64 bytes: one memory access per sample in the
 // common case.  `ref` is the paper's guide entry (Sec. 2.5, 3.2): the cell's
 // first node a, or ~i when one interval i covers the whole cell.  Beside it
@@ -186,26 +200,68 @@ __device__ inline int64_t xcd_block() {
     return x * q + (x < r ? x : r) + b / NXCD;
 }
 
+// The first d in [0, D] with off[d] > i (D + 1 if none; off[0..D]
+// non-decreasing), found by one wave (uniform i): each step probes 64 evenly
+// spaced offsets and keeps the bracket between the last one at or below i
+// and the first above it.  Every lane of the wave must call it.
+__device__ inline int32_t wave_upper_bound(const int64_t *off, int32_t D, int64_t i) {
+    const int32_t lane = threadIdx.x & 63;
+    int32_t lo = 0, hi = D + 1;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int32_t step = (hi - lo + 63) / 64;
+        const int32_t p = lo + lane * step;
+        const int32_t cnt = __popcll(__ballot(p < hi && off[p] <= i));  // a prefix of the lanes
+        if (cnt == 0) {
+            hi = lo;
+        } else {
+            const int32_t last = lo + (cnt - 1) * step;  // off[last] <= i
+            const int32_t next = lo + cnt * step;       // off[next] > i, or next >= hi
+            lo = last + 1;
+            hi = next < hi ? next : hi;
+        }
+    }
+    return lo;
+}
+
 // ---- launchers (defined in the .hip files) ----------------------------------
 
 hipError_t launch_build(const BuildArgs &a, hipStream_t st);
-hipError_t launch_sample(const Node *nodes, const Cell *cells, const Dist *dists,
+hipError_t launch_sample(const Node *nodes, const Wide *wide, const Cell *cells, const Dist *dists,
                          const int64_t *sample_off, int32_t D, int64_t n_total, int64_t m_total,
                          const uint64_t *u, int64_t S, int32_t *idx, double *x,
                          hipStream_t st);
-hipError_t launch_sample_2d(const Node *nodes, const Cell *cells, const Dist *dists,
+hipError_t launch_sample_2d(const Node *nodes, const Wide *wide, const Cell *cells, const Dist *dists,
                             int32_t D, int64_t n_total, const uint64_t *u2, int64_t S,
                             int32_t *rc, double *xy, hipStream_t st);
 hipError_t launch_sample_bsearch(const Node *nodes, const Cell *cells,
                                  const Dist *dists, bool cutpoint, const uint64_t *u,
                                  int64_t S, int32_t *idx, double *x, hipStream_t st);
+hipError_t launch_widen(const Node *nodes, const Cell *cells, const Dist *dists,
+                        const int64_t *elem_off, int32_t D, int64_t n_total, Wide *wide,
+                        hipStream_t st);
+hipError_t launch_depth(const Node *nodes, const Cell *cells, const Dist *dists,
+                        const int64_t *elem_off, int32_t D, int64_t n_total, uint32_t *depth,
+                        hipStream_t st);
+// the depth word of the status block
+constexpr int STATUS_DEPTH_OFFSET = 128;
 hipError_t launch_quantize(const float *v, const int64_t *elem_off, int32_t D,
                            int64_t n_total, uint32_t *out, double *scale,
                            uint32_t *status, hipStream_t st);
-hipError_t launch_backward(const Node *nodes, const Dist *dists, int32_t D,
-                           int64_t n_total, const int64_t *sample_off, const uint64_t *u,
-                           const int32_t *idx, const double *gx, int64_t S,
-                           const double *scale, double *grad_w, double *wsB, double *wsDv,
-                           double *wsA, hipStream_t st);
+// Scratch of the backward pass: per element the sums B and D, per
+// distribution A, per chunk of BACKWARD_CHUNK elements the combining pass's
+// head sum, link bits and carry.
+constexpr int64_t BACKWARD_CHUNK = 4096;
+__host__ __device__ inline int64_t backward_chunks(int64_t n_total) {
+    return (n_total + BACKWARD_CHUNK - 1) / BACKWARD_CHUNK;
+}
+struct BackwardScratch {
+    double *B, *Dv, *A, *head, *carry;
+    int32_t *link;
+};
+hipError_t launch_backward(const Node *nodes, const Dist *dists, const int64_t *elem_off,
+                           int32_t D, int64_t n_total, const int64_t *sample_off,
+                           const uint64_t *u, const int32_t *idx, const double *gx, int64_t S,
+                           const double *scale, double *grad_w, const BackwardScratch &w,
+                           hipStream_t st);
 
 }  // namespace rtf

@@ -97,26 +97,40 @@ struct Hit {
 // below u.  Otherwise the descent continues from the cell's tree root.  A
 // reference outside the forest, or a path longer than the forest has nodes,
 // can only come from a damaged workspace.
-__device__ inline Hit resolve(const Node *nodes, const Cell &c, const Dist &P, uint64_t u,
-                              int64_t n_total);
+__device__ inline Hit resolve(const Node *nodes, const Wide *wide, const Cell &c, const Dist &P,
+                              uint64_t u, int64_t n_total);
 
 __device__ inline int64_t cell_index(const Dist &P, uint64_t u) {
     return P.co + (int64_t)mulhi64(u, (uint64_t)P.m);
 }
 
-__device__ inline Hit descend(const Node *nodes, const Cell *cells, const Dist &P, uint64_t u,
-                              int64_t n_total) {
+__device__ inline Hit descend(const Node *nodes, const Wide *wide, const Cell *cells, const Dist &P,
+                              uint64_t u, int64_t n_total) {
     Cell c = load_cell(cells, cell_index(P, u));
     pin_cell(c);
-    return resolve(nodes, c, P, u, n_total);
+    return resolve(nodes, wide, c, P, u, n_total);
+}
+
+__device__ inline Wide load_wide(const Wide *wide, int64_t j) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(wide + j);
+    const uint4 a = p[0], b = p[1], c = p[2];  // 48 bytes of one line, in flight together
+    Wide r;
+    r.k = ((uint64_t)a.y << 32) | a.x;
+    r.kc[0] = ((uint64_t)a.w << 32) | a.z;
+    r.kc[1] = ((uint64_t)b.y << 32) | b.x;
+    r.r[0] = (int32_t)b.z;
+    r.r[1] = (int32_t)b.w;
+    r.r[2] = (int32_t)c.x;
+    r.r[3] = (int32_t)c.y;
+    return r;
 }
 
 // The sample's leaf from its cell record c (and, past the record, the tree).
 // The record's own answer is computed for every kind of cell with selects
 // only (a covered cell is a record holding no bounds); only a descent
 // branches.
-__device__ inline Hit resolve(const Node *nodes, const Cell &c, const Dist &P, uint64_t u,
-                              int64_t n_total) {
+__device__ inline Hit resolve(const Node *nodes, const Wide *wide, const Cell &c, const Dist &P,
+                              uint64_t u, int64_t n_total) {
     const bool covered = c.ref < 0;  // one interval covers the cell
     const int lim = covered ? 0 : (c.aux < 0 ? ~c.aux : CELL_BOUNDS);  // lower bounds held
     int j = 0;
@@ -133,22 +147,59 @@ __device__ inline Hit resolve(const Node *nodes, const Cell &c, const Dist &P, u
     h.lo = lo;
     h.hi = hi;
     if (!covered && c.aux >= 0 && u >= c.k[CELL_KEYS - 1]) {  // past the record: the tree
+        // Both bounds adjacent to the sampled leaf i are its ancestors when
+        // they lie inside the cell, so the descent meets U_i as the last key
+        // at or below u and U_{i+1} as the last key above it; only when i is
+        // the cell's last leaf is U_{i+1} read after the descent.
+        uint64_t klo = c.k[CELL_KEYS - 1], khi = 0;
+        bool hi_seen = false;
         int32_t jn = c.aux;
-        for (int64_t steps = 0; jn >= 0; ++steps) {
-            if (jn >= n_total || steps > n_total) {
-                h.i = -1;
-                return h;
+        if (wide) {
+            // collapsed nodes: two binary levels per record (Sec. 5)
+            for (int64_t steps = 0; jn >= 0; steps += 2) {
+                if (jn >= n_total || steps > n_total) {
+                    h.i = -1;
+                    return h;
+                }
+                const Wide wn = load_wide(wide, jn);
+                const bool right = u >= wn.k;
+                klo = right ? wn.k : klo;
+                khi = right ? khi : wn.k;
+                hi_seen = hi_seen || !right;
+                const int32_t g0 = right ? wn.r[2] : wn.r[0];
+                const int32_t g1 = right ? wn.r[3] : wn.r[1];
+                const uint64_t kc = right ? wn.kc[1] : wn.kc[0];
+                if (g0 == g1) {  // the child is a leaf
+                    jn = g0;
+                } else {
+                    const bool r2 = u >= kc;
+                    klo = r2 ? kc : klo;
+                    khi = r2 ? khi : kc;
+                    hi_seen = hi_seen || !r2;
+                    jn = r2 ? g1 : g0;
+                }
             }
-            const Node nd = load_node(nodes, jn);
-            jn = (u < nd.key) ? nd.c0 : nd.c1;
+        } else {
+            for (int64_t steps = 0; jn >= 0; ++steps) {
+                if (jn >= n_total || steps > n_total) {
+                    h.i = -1;
+                    return h;
+                }
+                const Node nd = load_node(nodes, jn);
+                const bool right = u >= nd.key;
+                klo = right ? nd.key : klo;
+                khi = right ? khi : nd.key;
+                hi_seen = hi_seen || !right;
+                jn = right ? nd.c1 : nd.c0;
+            }
         }
         h.i = ~(int64_t)jn;
         if (h.i < P.eo || h.i >= P.eo + P.n) {
             h.i = -1;
             return h;
         }
-        h.lo = nodes[h.i].key;
-        h.hi = (h.i + 1 < P.eo + P.n) ? nodes[h.i + 1].key : KEY_END;
+        h.lo = klo;
+        h.hi = hi_seen ? khi : ((h.i + 1 < P.eo + P.n) ? nodes[h.i + 1].key : KEY_END);
     }
     if (h.i < P.eo || h.i >= P.eo + P.n) h.i = -1;
     return h;
@@ -177,6 +228,7 @@ __device__ inline double position_of(const Node *nodes, const Dist &P, int64_t i
 
 template <bool BATCHED, bool WANT_X>
 __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
+                                                const Wide *__restrict__ wide,
                                                 const Cell *__restrict__ cells,
                                                 const Dist *__restrict__ dists,
                                                 const int64_t *__restrict__ sample_off,
@@ -188,7 +240,7 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
         const uint64_t us = __builtin_nontemporal_load(u + s);
         Hit h;
         h.i = -1;
-        if (!(P.flags & DIST_ZERO)) h = descend(nodes, cells, P, us, n_total);
+        if (!(P.flags & DIST_ZERO)) h = descend(nodes, wide, cells, P, us, n_total);
         if (h.i < 0) {
             idx[s] = -1;
             if (WANT_X) x[s] = __builtin_nan("");
@@ -232,8 +284,8 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
         pin_cell(cb);
         Hit ha, hb;
         ha.i = hb.i = -1;
-        if (!za) ha = resolve(nodes, ca, Pa, ua, n_total);
-        if (!zb) hb = resolve(nodes, cb, Pb, ub, n_total);
+        if (!za) ha = resolve(nodes, wide, ca, Pa, ua, n_total);
+        if (!zb) hb = resolve(nodes, wide, cb, Pb, ub, n_total);
         store(sa, Pa, ha, ua);
         if (has_b) store(sb, Pb, hb, ub);
     };
@@ -304,9 +356,9 @@ constexpr int LCELLS = 1024;    // 64 KB of records: two blocks per CU
 constexpr int STAGE_MIN = 2;
 template <bool WANT_X>
 __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void k_sample_staged(
-    const Node *__restrict__ nodes, const Cell *__restrict__ cells, const Dist *__restrict__ dists,
-    const int64_t *__restrict__ sample_off, int32_t D, int64_t n_total, const uint64_t *__restrict__ u,
-    int64_t S, int32_t *__restrict__ idx, double *__restrict__ x) {
+    const Node *__restrict__ nodes, const Wide *__restrict__ wide, const Cell *__restrict__ cells,
+    const Dist *__restrict__ dists, const int64_t *__restrict__ sample_off, int32_t D, int64_t n_total,
+    const uint64_t *__restrict__ u, int64_t S, int32_t *__restrict__ idx, double *__restrict__ x) {
     __shared__ uint4 s_cell[LCELLS * CELL_WORDS];
     const int64_t per = (S + gridDim.x - 1) / gridDim.x;
     const int64_t r0 = xcd_block() * per;
@@ -344,8 +396,8 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
                 Cell cb = load_cell(sc, (int64_t)mulhi64(ub, (uint64_t)P.m));
                 pin_cell(ca);
                 pin_cell(cb);
-                const Hit ha = resolve(nodes, ca, P, ua, n_total);
-                const Hit hb = resolve(nodes, cb, P, ub, n_total);
+                const Hit ha = resolve(nodes, wide, ca, P, ua, n_total);
+                const Hit hb = resolve(nodes, wide, cb, P, ub, n_total);
                 store(sa, P, ha, ua);
                 if (sb < e) store(sb, P, hb, ub);
             }
@@ -356,7 +408,7 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
                 const uint64_t us = __builtin_nontemporal_load(u + sa);
                 Hit h;
                 h.i = -1;
-                if (!zero) h = descend(nodes, cells, P, us, n_total);
+                if (!zero) h = descend(nodes, wide, cells, P, us, n_total);
                 store(sa, P, h, us);
             }
         }
@@ -374,8 +426,9 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
 // threads, two per CU, one pair per lane and step.
 template <bool WANT_X>
 __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void k_sample_2d_staged(
-    const Node *__restrict__ nodes, const Cell *__restrict__ cells, const Dist *__restrict__ dists, int32_t D,
-    int64_t n_total, const uint64_t *__restrict__ u2, int64_t S, int32_t *__restrict__ rc,
+    const Node *__restrict__ nodes, const Wide *__restrict__ wide, const Cell *__restrict__ cells,
+    const Dist *__restrict__ dists, int32_t D, int64_t n_total, const uint64_t *__restrict__ u2, int64_t S,
+    int32_t *__restrict__ rc,
     double *__restrict__ xy) {
     typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
     typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
@@ -398,7 +451,7 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
         f64x2 pos = {__builtin_nan(""), __builtin_nan("")};
         Hit hr;
         hr.i = -1;
-        if (!mzero) hr = resolve(nodes, cr, M, uu.x, n_total);
+        if (!mzero) hr = resolve(nodes, wide, cr, M, uu.x, n_total);
         const int64_t r = hr.i - M.eo;
         // the marginal must have one weight per row distribution 1..D-1
         if (hr.i >= 0 && 1 + r < D) {
@@ -407,7 +460,7 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
             const Dist R = dists[1 + r];
             Hit hc;
             hc.i = -1;
-            if (!(R.flags & DIST_ZERO)) hc = descend(nodes, cells, R, uu.y, n_total);
+            if (!(R.flags & DIST_ZERO)) hc = descend(nodes, wide, cells, R, uu.y, n_total);
             if (hc.i >= 0) {
                 out.y = (int32_t)(hc.i - R.eo);
                 if (WANT_X) pos.y = position(R, hc, uu.y);
@@ -498,7 +551,7 @@ inline int grid_for(int64_t S) {
 
 }  // namespace
 
-hipError_t launch_sample(const Node *nodes, const Cell *cells, const Dist *dists,
+hipError_t launch_sample(const Node *nodes, const Wide *wide, const Cell *cells, const Dist *dists,
                          const int64_t *sample_off, int32_t D, int64_t n_total, int64_t m_total,
                          const uint64_t *u, int64_t S, int32_t *idx, double *x,
                          hipStream_t st) {
@@ -509,30 +562,30 @@ hipError_t launch_sample(const Node *nodes, const Cell *cells, const Dist *dists
         int64_t nb = (S + 4 * SB_T - 1) / (4 * SB_T);
         nb = nb < 512 ? nb : 512;
         if (x)
-            hipLaunchKernelGGL((k_sample_staged<true>), dim3((unsigned)nb), dim3(SB_T), 0, st, nodes, cells, dists,
+            hipLaunchKernelGGL((k_sample_staged<true>), dim3((unsigned)nb), dim3(SB_T), 0, st, nodes, wide, cells, dists,
                                sample_off, D, n_total, u, S, idx, x);
         else
-            hipLaunchKernelGGL((k_sample_staged<false>), dim3((unsigned)nb), dim3(SB_T), 0, st, nodes, cells,
+            hipLaunchKernelGGL((k_sample_staged<false>), dim3((unsigned)nb), dim3(SB_T), 0, st, nodes, wide, cells,
                                dists, sample_off, D, n_total, u, S, idx, x);
         return hipGetLastError();
     }
     const dim3 g(batched ? grid_for((S + SCHUNK / 256 - 1) / (SCHUNK / 256)) : grid_for(S)), b(256);
     if (batched && x)
-        hipLaunchKernelGGL((k_sample<true, true>), g, b, 0, st, nodes, cells, dists, sample_off,
+        hipLaunchKernelGGL((k_sample<true, true>), g, b, 0, st, nodes, wide, cells, dists, sample_off,
                            D, n_total, u, S, idx, x);
     else if (batched)
-        hipLaunchKernelGGL((k_sample<true, false>), g, b, 0, st, nodes, cells, dists,
+        hipLaunchKernelGGL((k_sample<true, false>), g, b, 0, st, nodes, wide, cells, dists,
                            sample_off, D, n_total, u, S, idx, x);
     else if (x)
-        hipLaunchKernelGGL((k_sample<false, true>), g, b, 0, st, nodes, cells, dists,
+        hipLaunchKernelGGL((k_sample<false, true>), g, b, 0, st, nodes, wide, cells, dists,
                            sample_off, D, n_total, u, S, idx, x);
     else
-        hipLaunchKernelGGL((k_sample<false, false>), g, b, 0, st, nodes, cells, dists,
+        hipLaunchKernelGGL((k_sample<false, false>), g, b, 0, st, nodes, wide, cells, dists,
                            sample_off, D, n_total, u, S, idx, x);
     return hipGetLastError();
 }
 
-hipError_t launch_sample_2d(const Node *nodes, const Cell *cells, const Dist *dists,
+hipError_t launch_sample_2d(const Node *nodes, const Wide *wide, const Cell *cells, const Dist *dists,
                             int32_t D, int64_t n_total, const uint64_t *u2, int64_t S,
                             int32_t *rc, double *xy, hipStream_t st) {
     // two blocks per CU, each copying the marginal's records once
@@ -540,10 +593,10 @@ hipError_t launch_sample_2d(const Node *nodes, const Cell *cells, const Dist *di
     nb = nb < 512 ? nb : 512;
     const dim3 g((unsigned)nb), b(SB_T);
     if (xy)
-        hipLaunchKernelGGL((k_sample_2d_staged<true>), g, b, 0, st, nodes, cells, dists, D, n_total, u2,
+        hipLaunchKernelGGL((k_sample_2d_staged<true>), g, b, 0, st, nodes, wide, cells, dists, D, n_total, u2,
                            S, rc, xy);
     else
-        hipLaunchKernelGGL((k_sample_2d_staged<false>), g, b, 0, st, nodes, cells, dists, D, n_total,
+        hipLaunchKernelGGL((k_sample_2d_staged<false>), g, b, 0, st, nodes, wide, cells, dists, D, n_total,
                            u2, S, rc, xy);
     return hipGetLastError();
 }

@@ -125,3 +125,76 @@ def assert_forest(f, ref, what=""):
     assert bx.size == 0, f"{what} {bx.size} cell records differ, first at {bx[:5]}: " \
         f"gpu {ckeys[bx[:2]].tolist()} {cc1[bx[:2]].tolist()} ref {ek[bx[:2]].tolist()} " \
         f"{ec1[bx[:2]].tolist()}"
+
+
+def expected_wide(ref):
+    """The collapsed records rtf_forest_widen must write, derived from the
+    oracle forest: (node indices j, int64 rows [len(j), 5] holding k, kc0,
+    kc1 and the reference pairs (r0, r1), (r2, r3) as int32 pairs)."""
+    MAX = np.uint64(TWO64 - 1)
+    key, child, table = ref.key, ref.child, ref.table.astype(np.int64)
+    eo, co = ref.elem_off.astype(np.int64), ref.cell_off.astype(np.int64)
+    _, aux = expected_cells(ref)
+    j = np.nonzero(key != MAX)[0]
+    g = _cells_of(key[j], j, eo, co)
+    deep = (table[g] >= 0) & (aux[g] >= 0) & (table[g] != j)
+    j = j[deep]
+    rows = np.zeros((j.size, 5), np.int64)
+    rows[:, 0] = key[j].view(np.int64)
+    refs = []
+    for s in (0, 1):
+        c = child[j, s].astype(np.int64)
+        inner = c >= 0
+        cc = np.where(inner, c, 0)
+        rows[:, 1 + s] = np.where(inner, key[cc], np.uint64(0)).view(np.int64)
+        refs.append(np.where(inner, child[cc, 0], c).astype(np.int32))
+        refs.append(np.where(inner, child[cc, 1], c).astype(np.int32))
+    pair = lambda a, b: (b.astype(np.int64) << 32) | (a.astype(np.int64) & 0xFFFFFFFF)  # noqa: E731
+    rows[:, 3] = pair(refs[0], refs[1])
+    rows[:, 4] = pair(refs[2], refs[3])
+    return j, rows
+
+
+def assert_wide(f, ref, what=""):
+    j, rows = expected_wide(ref)
+    got = f.wide_view().cpu().numpy()[j, :5]
+    bad = np.nonzero((got != rows).any(axis=1))[0]
+    assert bad.size == 0, f"{what} {bad.size} of {j.size} collapsed records differ, first nodes " \
+        f"{j[bad[:5]]}: gpu {got[bad[:2]].tolist()} ref {rows[bad[:2]].tolist()}"
+    return j.size
+
+
+def alg2_reads(ref, u, d=0):
+    """Reads Alg. 2 makes for each uniform of distribution d on the oracle
+    forest: the guide entry plus one per node visited."""
+    key, child, table = ref.key, ref.child, ref.table.astype(np.int64)
+    co, m = int(ref.cell_off[d]), int(ref.cell_off[d + 1] - ref.cell_off[d])
+    u = np.asarray(u, np.uint64)
+    g = ((u.astype(object) * m) >> 64).astype(np.int64)
+    j = table[co + g]
+    reads = np.ones(u.size, np.int64)
+    act = j >= 0
+    while act.any():
+        ja = j[act]
+        reads[act] += 1
+        j[act] = np.where(u[act] < key[ja], child[ja, 0], child[ja, 1])
+        act = j >= 0
+    return reads
+
+
+def forest_depth(ref):
+    """The deepest search of the oracle forest (what rtf_forest_depth
+    reports): Alg. 2's reads for u = U_i over the leaves with positive
+    weight, every distribution."""
+    MAX = np.uint64(TWO64 - 1)
+    best = 0
+    eo = ref.elem_off
+    for d in range(eo.size - 1):
+        if int(ref.W[d]) == 0:
+            continue
+        k = ref.key[eo[d]:eo[d + 1]]
+        nxt = np.append(k[1:], MAX)
+        live = (k != MAX) & ((nxt != k) | (nxt == MAX))
+        if live.any():
+            best = max(best, int(alg2_reads(ref, k[live], d).max()))
+    return best
