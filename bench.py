@@ -84,36 +84,67 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--profile", action="store_true",
                    help="few steps, no baselines (for rocprofv3 runs)")
-    p.add_argument("--config", choices=["h24", "c3", "c4", "c5", "table1"], default="h24",
+    p.add_argument("--config", choices=["h24", "c3", "c4", "c5", "table1", "grad1"],
+                   default="h24",
                    help="h24: the benchmark line; c3/c4/c5: the 2D map, the uneven batch and "
                         "the differentiable workload; table1: load counts and speed on the "
                         "paper's high-dynamic-range densities (extra measurements)")
     return p.parse_args()
 
 
-def sample_bytes_model(key, child, table, K, aux, m, u):
-    """Replay Alg. 2 with the cell records on the host (exported forest,
-    subsample of the uniforms) and return the mean useful bytes a sample reads
-    beyond its streams (the 64-byte cell record, plus 16 bytes per node record
-    of the descent and 32 bytes for the two keys of the position when the
-    record does not resolve the sample), the mean number of dependent random
-    loads per sample (the record, each node, the key pair), the mean descent
-    length and the fraction of samples the record resolves."""
+def replay_lookup(key, child, table, K, aux, m, u, wide=None):
+    """Replay this library's lookup on the host (exported forest): the 64-byte
+    cell record, and only when it does not resolve the sample, the descent
+    from the cell tree's root, one 16-byte node per binary level, or with
+    `wide` (the collapsed records as int64 [n, 8]) one 64-byte record per two
+    levels.  The descent meets both keys of the sampled interval except when
+    it ends at its cell's last leaf; then one more key is read for the
+    position.  Returns per sample: whether it descended, the records the
+    descent read, and whether the upper key was read after it."""
     g = ((u.astype(object) * m) >> 64).astype(np.int64)
     ref = table[g].astype(np.int64)
     ax = aux[g].astype(np.int64)
     deeper = (ref >= 0) & (ax >= 0) & (u >= K[g, K.shape[1] - 1])
     j = np.where(deeper, ax, -1).astype(np.int64)
     visits = np.zeros(u.size, np.int64)
+    hi_seen = np.zeros(u.size, bool)
+    if wide is not None:
+        wk = wide[:, 0].view(np.uint64)
+        wc = wide[:, 1:3].view(np.uint64)
+        wr = wide[:, 3:5].copy().view(np.int32).reshape(-1, 4).astype(np.int64)
     active = j >= 0
     while active.any():
-        ja = j[active]
+        ja, ua = j[active], u[active]
         visits[active] += 1
-        go_left = u[active] < key[ja]
-        j[active] = np.where(go_left, child[ja, 0], child[ja, 1])
+        if wide is None:
+            right = ua >= key[ja]
+            hs = ~right
+            nj = np.where(right, child[ja, 1], child[ja, 0])
+        else:
+            right = ua >= wk[ja]
+            g0 = np.where(right, wr[ja, 2], wr[ja, 0])
+            g1 = np.where(right, wr[ja, 3], wr[ja, 1])
+            kc = np.where(right, wc[ja, 1], wc[ja, 0])
+            leaf = g0 == g1
+            r2 = ua >= kc
+            hs = ~right | (~leaf & ~r2)
+            nj = np.where(leaf, g0, np.where(r2, g1, g0))
+        hi_seen[active] |= hs
+        j[active] = nj
         active = j >= 0
-    extra = CELL_B + deeper * (NODE_B * visits + 2 * NODE_B)
-    loads = 1 + deeper * (visits + 1)
+    late = deeper & ~hi_seen
+    return deeper, visits, late
+
+
+def sample_bytes_model(key, child, table, K, aux, m, u, wide=None):
+    """Mean useful bytes a sample reads beyond its streams (the 64-byte cell
+    record, the records of a descent and the late upper key), the mean number
+    of dependent random reads per sample, the mean descent length and the
+    fraction of samples the record resolves."""
+    deeper, visits, late = replay_lookup(key, child, table, K, aux, m, u, wide)
+    rec_b = NODE_B if wide is None else 64
+    extra = CELL_B + deeper * (rec_b * visits + NODE_B * late)
+    loads = 1 + deeper * (visits + late)
     return float(extra.mean()), float(loads.mean()), \
         float(visits[deeper].mean()) if deeper.any() else 0.0, float(1.0 - deeper.mean())
 
@@ -133,23 +164,10 @@ def loads_forest_alg2(key, child, table, m, u):
     return loads
 
 
-def loads_forest_records(key, child, table, K, aux, m, u):
-    """This library's lookup: the 64-byte cell record, and only when it does
-    not resolve the sample, the node records of the descent plus the key pair
-    of the position."""
-    g = ((u.astype(object) * m) >> 64).astype(np.int64)
-    ref = table[g].astype(np.int64)
-    ax = aux[g].astype(np.int64)
-    deeper = (ref >= 0) & (ax >= 0) & (u >= K[g, K.shape[1] - 1])
-    j = np.where(deeper, ax, -1).astype(np.int64)
-    visits = np.zeros(u.size, np.int64)
-    active = j >= 0
-    while active.any():
-        ja = j[active]
-        visits[active] += 1
-        j[active] = np.where(u[active] < key[ja], child[ja, 0], child[ja, 1])
-        active = j >= 0
-    return 1 + deeper * (visits + 1)
+def loads_forest_records(key, child, table, K, aux, m, u, wide=None):
+    """Dependent reads per sample of this library's lookup (replay_lookup)."""
+    deeper, visits, late = replay_lookup(key, child, table, K, aux, m, u, wide)
+    return 1 + deeper * (visits + late)
 
 
 def loads_bisection(key, lo, hi, u):
@@ -248,7 +266,8 @@ def main():
               "one distribution is built and sampled on a single device", file=sys.stderr)
         sys.exit(2)
     if args.config != "h24":
-        {"c3": run_c3, "c4": run_c4, "c5": run_c5, "table1": run_table1}[args.config](args)
+        {"c3": run_c3, "c4": run_c4, "c5": run_c5, "table1": run_table1,
+         "grad1": run_grad1}[args.config](args)
         return
     import ctypes
     import torch
@@ -573,14 +592,25 @@ def run_table1(args):
         t_bs = event_time(lambda: rtf.sample_bsearch(f, u, out=(idx, x)), args.steps)
         t_cb = event_time(lambda: rtf.sample_cutpoint_bsearch(f, u, out=(idx, x)), args.steps)
         key, child, table, W, (K, aux) = f.export(with_cells=True)
+        rtf.sample(f, u, out=(idx, x))
+        ref_idx = idx.clone()
+        # the same forest with collapsed 4-ary records for the descended cells
+        t_w = event_time(lambda: f.widen(ws=getattr(f, "wide_ws", None)), args.steps)
+        t_sw = event_time(lambda: rtf.sample(f, u, out=(idx, x)), args.steps)
+        assert torch.equal(idx, ref_idx), "collapsed and binary descents differ"
+        wide = f.wide_view().cpu().numpy()
         out[fam] = {
             "loads_cutpoint_bisection": load_stats(loads_cutpoint(key, table, m, sub)),
             "loads_forest_alg2": load_stats(loads_forest_alg2(key, child, table, m, sub)),
             "loads_forest_records": load_stats(loads_forest_records(key, child, table, K, aux, m,
                                                                     sub)),
-            "samples_s": {"forest": S / (t_s * 1e-3), "cutpoint_bisection": S / (t_cb * 1e-3),
+            "loads_forest_records_collapsed": load_stats(
+                loads_forest_records(key, child, table, K, aux, m, sub, wide=wide)),
+            "samples_s": {"forest": S / (t_s * 1e-3), "forest_collapsed": S / (t_sw * 1e-3),
+                          "cutpoint_bisection": S / (t_cb * 1e-3),
                           "binary_search": S / (t_bs * 1e-3)},
             "build_ms": t_b,
+            "widen_ms": t_w,
         }
     res = common(METRIC, "samples/s", out[wl.TABLE1_FAMILIES[0]]["samples_s"]["forest"],
                  S / out[wl.TABLE1_FAMILIES[0]]["samples_s"]["forest"] * 1e3, args, "u64",
@@ -590,10 +620,15 @@ def run_table1(args):
     print(json.dumps(res), flush=True)
 
 
-def batch_ratio(args):
-    """Guide cells per weight for the batched workloads: --cell-ratio, else
-    the ratio the autotuner picks for one distribution at n = 2^24 (1/4)."""
-    return args.cell_ratio if args.cell_ratio is not None else 0.25
+def batch_choice(args, v, u, eo, so):
+    """Guide cells per weight and descent form for a batched workload:
+    --cell-ratio fixes the ratio (binary descent), else the autotuner times
+    quantise + build (+ collapse) + sample over its candidates on this data."""
+    if args.cell_ratio is not None:
+        return args.cell_ratio, False, {"source": "fixed"}
+    from paper_1901_05423_amd import tune
+    r, c, times = tune.best_batched(v, u, eo, so, use_cache=False)
+    return r, c, {"source": "tuner", "ms_by_ratio_and_collapsed": times}
 
 
 def run_c4(args):
@@ -611,46 +646,79 @@ def run_c4(args):
     v, u = torch.from_numpy(v_h).to(dev), torch.from_numpy(u_h).to(dev)
     eo, so = torch.from_numpy(eo_h).to(dev), torch.from_numpy(so_h).to(dev)
     n, S, D = int(eo_h[-1]), int(so_h[-1]), eo_h.size - 1
-    ratio = batch_ratio(args)
+    ratio, collapsed, tuning = batch_choice(args, v, u, eo, so)
     co = rtf.cells_like(eo, ratio)
     mt = int(co[-1].item())
-    plan = BatchedPlan(eo, co, so, n, mt, S)
+    plan = BatchedPlan(eo, co, so, n, mt, S, collapsed=collapsed)
     for _ in range(args.warmup):
         plan.run(v, u)
     plan.check()
     t_eager = event_time(lambda: plan.run(v, u), args.steps)
     g = plan.capture(v, u)
     t_graph = event_time(g.replay, args.steps)
-    # per-distribution launches of the same library (one quantise, build and
-    # sample call sequence per distribution)
-    forests = []
+    # per-distribution launches of the same library: one quantise, build and
+    # sample call sequence per distribution, every buffer preallocated (one
+    # workspace per distribution, slices of shared inputs and outputs), so
+    # the loop times launches only
+    import ctypes
+    L = rtf.lib()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    n_d = np.diff(eo_h)
+    m_d = np.maximum(1, np.round(ratio * n_d)).astype(np.int64)
+    nb = np.array([L.rtf_workspace_bytes(int(a), int(b)) for a, b in zip(n_d, m_d)], np.int64)
+    wo = np.concatenate([[0], np.cumsum(nb)])
+    ws_all = torch.empty(int(wo[-1]), dtype=torch.uint8, device=dev)
+    q_all = torch.empty(n, dtype=torch.uint32, device=dev)
+    sc_all = torch.empty(D, dtype=torch.float64, device=dev)
+    idx_all = torch.empty(S, dtype=torch.int32, device=dev)
+    x_all = torch.empty(S, dtype=torch.float64, device=dev)
+    descs = (rtf.rtf_forest * D)()
+    P = ctypes.c_void_p
+    calls = [(P(v.data_ptr() + 4 * int(eo_h[d])), int(n_d[d]), P(q_all.data_ptr() + 4 * int(eo_h[d])),
+              P(sc_all.data_ptr() + 8 * d), int(m_d[d]), P(ws_all.data_ptr() + int(wo[d])),
+              int(nb[d]), ctypes.byref(descs[d]), P(u.data_ptr() + 8 * int(so_h[d])),
+              int(so_h[d + 1] - so_h[d]), P(idx_all.data_ptr() + 4 * int(so_h[d])),
+              P(x_all.data_ptr() + 8 * int(so_h[d]))) for d in range(D)]
+    quant, build1, samp = L.rtf_quantize_f32, L.rtf_build, L.rtf_sample
+
+    def per_distribution():
+        for (vp, nd, qp, sp, md, wp, wb, dp, up, sd, ip, xp) in calls:
+            quant(vp, None, 1, nd, qp, sp, None, st)
+            build1(qp, nd, md, wp, wb, st, dp)
+            samp(dp, up, sd, ip, xp, st)
+
+    per_distribution()
     torch.cuda.synchronize()
+    assert torch.equal(idx_all, plan.idx), "per-distribution and batched indices differ"
     t0 = time.perf_counter()
-    for d in range(D):
-        a, b = int(eo_h[d]), int(eo_h[d + 1])
-        q, _ = rtf.quantize(v[a:b])
-        f = rtf.build(q, max(1, int(round(ratio * (b - a)))))
-        rtf.sample(f, u[int(so_h[d]):int(so_h[d + 1])])
-        forests.append(f)
-        if len(forests) > 64:
-            forests.pop(0)
+    per_distribution()
     torch.cuda.synchronize()
     t_b3 = (time.perf_counter() - t0) * 1e3
+    t_b3_gpu = event_time(per_distribution, 1)
     res = common(METRIC, "samples/s", S / (t_graph * 1e-3), t_graph, args, "u64",
                  f"C4: {D} distributions, sizes log-uniform in [16, 65536] (n_total={n}), "
-                 f"uniform or Pareto(1.2) weights, m_d={ratio:g}n_d, {S} uniforms (64 per 1k weights), "
-                 "quantise + build + sample with x",
+                 f"uniform or Pareto(1.2) weights, m_d={ratio:g}n_d ({tuning['source']}), "
+                 f"{'collapsed' if collapsed else 'binary'} descent, {S} uniforms (64 per 1k "
+                 "weights), quantise + build + sample with x",
+                 cell_ratio=ratio, collapsed=collapsed, tuning=tuning,
                  elements_per_s=n / (t_graph * 1e-3), ms_eager=t_eager, ms_graph=t_graph,
                  ms_per_distribution_launches=t_b3,
+                 ms_per_distribution_launches_events=t_b3_gpu,
+                 per_distribution_note="preallocated buffers, one quantise + build + sample "
+                                       "call sequence per distribution on one stream",
                  speedup_vs_per_distribution=t_b3 / t_graph)
     print(json.dumps(res), flush=True)
 
 
 def run_c3(args):
     """4096 x 4096 map: marginal + 4096 rows quantised and built as one batch,
-    2^27 (row, column) pairs with sub-pixel positions."""
+    2^27 (row, column) pairs with sub-pixel positions.  The guide size and the
+    descent form (binary nodes or collapsed 4-ary records) are tuned on this
+    map: build (+ collapse) + 2D sampling timed per candidate."""
+    import ctypes
     import torch
     import paper_1901_05423_amd as rtf
+    from paper_1901_05423_amd import tune
     from paper_1901_05423_amd import workloads as wl
     r = wl.rng(wl.C3_MAP_2D)
     img, marg = wl.map_2d(r)
@@ -663,41 +731,102 @@ def run_c3(args):
     v, u2 = torch.from_numpy(v_h).to(dev), torch.from_numpy(u_h).to(dev)
     eo = torch.from_numpy(eo_h).to(dev)
     n = int(eo_h[-1])
-    ratio = batch_ratio(args)
-    co = rtf.cells_like(eo, ratio)
-    mt = int(co[-1].item())
     q = torch.empty(n, dtype=torch.uint32, device=dev)
     scale = torch.empty(R + 1, dtype=torch.float64, device=dev)
-    ws = torch.empty(rtf.lib().rtf_workspace_bytes_batched(R + 1, n, mt), dtype=torch.uint8,
-                     device=dev)
     rc = torch.empty(2 * pairs, dtype=torch.int32, device=dev)
     xy = torch.empty(2 * pairs, dtype=torch.float64, device=dev)
-    st = {}
+    wide_ws = torch.empty(rtf.lib().rtf_wide_workspace_bytes(n), dtype=torch.uint8, device=dev)
 
-    def build():
-        rtf.quantize(v, eo, out=(q, scale))
-        st["f"] = rtf.build_batched(q, eo, co) if "f" not in st else _rebuild(st["f"])
+    def setup(ratio):
+        co = rtf.cells_like(eo, ratio)
+        mt = int(co[-1].item())
+        ws = torch.empty(rtf.lib().rtf_workspace_bytes_batched(R + 1, n, mt), dtype=torch.uint8,
+                         device=dev)
+        desc = rtf.rtf_forest()
 
-    def _rebuild(f):
-        import ctypes
-        rtf._check(rtf.lib().rtf_build_batched(rtf._ptr(q), rtf._ptr(eo), rtf._ptr(co), R + 1, n,
-                                               mt, rtf._ptr(f.ws), f.ws.numel(), rtf._stream(),
-                                               ctypes.byref(f.desc)), "rtf_build_batched")
-        return f
+        def build():
+            rtf.quantize(v, eo, out=(q, scale))
+            rtf._check(rtf.lib().rtf_build_batched(rtf._ptr(q), rtf._ptr(eo), rtf._ptr(co), R + 1,
+                                                   n, mt, rtf._ptr(ws), ws.numel(), rtf._stream(),
+                                                   ctypes.byref(desc)), "rtf_build_batched")
+        build()
+        f = rtf.Forest(ws, desc, dev)
+        return co, f, build
 
-    build()
+    def widen(f):
+        f.widen(ws=wide_ws)
+
+    def sample(f):
+        rtf.sample_2d(f, u2, out=(rc, xy))
+
+    if args.cell_ratio is not None:
+        candidates, source = [(args.cell_ratio, False)], "fixed"
+    else:
+        candidates, source = [(0.125, False), (0.25, False), (0.5, False), (0.25, True),
+                              (0.5, True), (1.0, True)], "tuner"
+    times = {}
+    for ratio, coll in candidates:
+        _, f, build = setup(ratio)
+
+        def chain():
+            build()
+            if coll:
+                widen(f)
+            sample(f)
+        times[f"{ratio}|{int(coll)}"] = tune._time_ms(chain, 3)
+        del f
+    best = min(times, key=times.get)
+    ratio, collapsed = float(best.split("|")[0]), bool(int(best.split("|")[1]))
+    co, f, build = setup(ratio)
     torch.cuda.synchronize()
-    st["f"].check()
+    f.check()
     t_build = event_time(build, args.steps)
-    t_sample = event_time(lambda: rtf.sample_2d(st["f"], u2, out=(rc, xy)), args.steps)
-    ms = t_build + t_sample
+    t_sample = event_time(lambda: sample(f), args.steps)
+    rc_bin = rc.clone()
+    # the same forest with collapsed 4-ary records for the descended row cells
+    t_widen = event_time(lambda: widen(f), args.steps)
+    t_sample_w = event_time(lambda: sample(f), args.steps)
+    assert torch.equal(rc, rc_bin), "collapsed and binary descents differ"
+    key, child, table, W, (K, aux) = f.export(with_cells=True)
+    wide = f.wide_view().cpu().numpy()
+    # row lookups replayed on the host for 2^20 pairs (rows from the GPU run)
+    co_h = co.cpu().numpy()
+    rows_h = rc_bin.view(-1, 2)[: 1 << 20, 0].cpu().numpy()
+    uc = u_h[1::2][: 1 << 20]
+    loads = {"binary": [], "collapsed": []}
+    for r_ in np.unique(rows_h):
+        sel = rows_h == r_
+        d = 1 + int(r_)
+        lo_e, hi_e = int(eo_h[d]), int(eo_h[d + 1])
+        lo_c, m_d = int(co_h[d]), int(co_h[d + 1] - co_h[d])
+        loc = lambda a: np.where(a >= 0, a - lo_e, ~(~a - lo_e))  # noqa: E731
+        kd = key[lo_e:hi_e]
+        cd = loc(child[lo_e:hi_e].astype(np.int64))
+        td = loc(table[lo_c:lo_c + m_d].astype(np.int64))
+        ad = aux[lo_c:lo_c + m_d].astype(np.int64)
+        ad = np.where(ad >= 0, ad - lo_e, ad)
+        wd = wide[lo_e:hi_e].copy()
+        for col in (3, 4):
+            pr = wd[:, col].copy().view(np.int32).astype(np.int64)
+            wd[:, col] = loc(pr).astype(np.int32).view(np.int64)
+        for mode, wv in (("binary", None), ("collapsed", wd)):
+            loads[mode].append(loads_forest_records(kd, cd, td, K[lo_c:lo_c + m_d], ad, m_d,
+                                                    uc[sel], wide=wv))
+    row_loads = {k: load_stats(np.concatenate(v_)) for k, v_ in loads.items()}
+    ms = t_build + (t_widen + t_sample_w if collapsed else t_sample)
     res = common(METRIC, "pairs/s", pairs / (ms * 1e-3), ms, args, "u64",
                  "C3: 4096x4096 log-normal(0,1.5) map + 8 hot spots (1e4, sigma 3 px); marginal + "
-                 f"4096 rows quantised and built as one batch (m_d={ratio:g}n_d); 2^27 (row, col) pairs + "
+                 f"4096 rows quantised and built as one batch (m_d={ratio:g}n_d, {source}); "
+                 f"{'collapsed' if collapsed else 'binary'} descent; 2^27 (row, col) pairs + "
                  "sub-pixel positions",
-                 ms_build=t_build, ms_sample=t_sample,
+                 cell_ratio=ratio, collapsed=collapsed,
+                 tuning={"source": source, "ms_build_plus_sample": times},
+                 ms_build=t_build, ms_sample=t_sample, ms_widen=t_widen,
+                 ms_sample_collapsed=t_sample_w,
                  build_melem_s=n / (t_build * 1e-3) / 1e6,
-                 sample_only_pairs_s=pairs / (t_sample * 1e-3))
+                 sample_only_pairs_s=pairs / (t_sample * 1e-3),
+                 sample_only_pairs_s_collapsed=pairs / (t_sample_w * 1e-3),
+                 row_lookup_loads=row_loads)
     print(json.dumps(res), flush=True)
 
 
@@ -718,9 +847,10 @@ def run_c5(args):
     so = torch.arange(D + 1, dtype=torch.int64, device=dev) * per
     v = torch.nn.functional.softplus(z).reshape(-1).contiguous()
     from paper_1901_05423_amd.plan import BatchedPlan
-    md = max(1, int(round(nd * batch_ratio(args))))
+    ratio, collapsed, tuning = batch_choice(args, v, u, eo, so)
+    md = max(1, int(round(nd * ratio)))
     co = torch.arange(D + 1, dtype=torch.int64, device=dev) * md
-    plan = BatchedPlan(eo, co, so, D * nd, D * md, D * per)
+    plan = BatchedPlan(eo, co, so, D * nd, D * md, D * per, collapsed=collapsed)
     plan.run(v, u)
     plan.check()
     f = plan
@@ -736,10 +866,40 @@ def run_c5(args):
     t_bwd = event_time(bwd, args.steps)
     S = D * per
     res = common(METRIC, "samples/s", S / ((t_fwd + t_bwd) * 1e-3), t_fwd + t_bwd, args, "u64",
-                 f"C5: 256 distributions x 4096 softplus(N(0,1)) weights, m_d={md}, 2^20 uniforms each; "
-                 "forward quantise + build + sample with x, backward dL/dw of L = sum sin(7x)",
+                 f"C5: 256 distributions x 4096 softplus(N(0,1)) weights, m_d={md} "
+                 f"({tuning['source']}), {'collapsed' if collapsed else 'binary'} descent, 2^20 "
+                 "uniforms each; forward quantise + build + sample with x, backward dL/dw of "
+                 "L = sum sin(7x)",
+                 cell_ratio=ratio, collapsed=collapsed, tuning=tuning,
                  ms_forward=t_fwd, ms_backward=t_bwd,
                  forward_samples_s=S / (t_fwd * 1e-3), backward_samples_s=S / (t_bwd * 1e-3))
+    print(json.dumps(res), flush=True)
+
+
+def run_grad1(args):
+    """The adjoint of one large distribution: 2^22 uniform(0,1] weights,
+    2^24 uniforms, L = sum sin(7x); forward (quantise + build + sample) and
+    rtf_backward, whose combining pass spreads the distribution over all
+    CUs."""
+    import torch
+    import paper_1901_05423_amd as rtf
+    from paper_1901_05423_amd import workloads as wl
+    n, S = 1 << 22, 1 << 24
+    r = wl.rng(wl.H24_UNIFORM)
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(wl.weights_uniform(r, n)).to(dev)
+    u = torch.from_numpy(wl.uniforms(r, S)).to(dev)
+    q, scale = rtf.quantize(v)
+    f = rtf.build(q, n // 4)
+    idx, x = rtf.sample(f, u)
+    gx = 7.0 * torch.cos(7.0 * x)
+    bws = torch.empty(rtf.lib().rtf_backward_workspace_bytes(1, n), dtype=torch.uint8,
+                      device=dev)
+    t_bwd = event_time(lambda: rtf.backward(f, u, idx, gx, scale, ws=bws), args.steps)
+    res = common(METRIC, "samples/s", S / (t_bwd * 1e-3), t_bwd, args, "u64",
+                 "one distribution of 2^22 uniform(0,1] weights, m = n/4, 2^24 uniforms: "
+                 "rtf_backward of L = sum sin(7x)",
+                 ms_backward=t_bwd, backward_weights_s=n / (t_bwd * 1e-3))
     print(json.dumps(res), flush=True)
 
 

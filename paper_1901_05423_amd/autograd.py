@@ -14,19 +14,31 @@ from . import backward, build_batched, cells_like, quantize, sample_batched
 
 class RTFSample(torch.autograd.Function):
     """x = RTFSample.apply(v, u, elem_off, sample_off, cell_ratio)
+       x = RTFSample.apply(v, u, plan)
 
     v           float32[n_total] non-negative weights (requires_grad allowed)
     u           uint64[S] uniforms; sample_off int64[D+1] splits them by
                 distribution; elem_off int64[D+1] splits v
     cell_ratio  guide cells per weight (m_d = round(ratio * n_d), at least 1)
+    plan        a plan.DiffPlan for these shapes: every buffer preallocated,
+                nothing read back, so forward and backward can be captured
+                in a HIP graph; x is then a view of the plan's buffer
     Returns x float64[S].
     """
 
     @staticmethod
-    def forward(ctx, v, u, elem_off, sample_off, cell_ratio=1.0):
+    def forward(ctx, v, u, elem_off, sample_off=None, cell_ratio=1.0):
+        from .plan import DiffPlan
+        if isinstance(elem_off, DiffPlan):
+            plan = elem_off
+            _, x = plan.run(v.detach(), u)
+            ctx.plan = plan
+            ctx.save_for_backward(u)
+            return x.view(-1)
         q, scale = quantize(v.detach().contiguous(), elem_off)
         f = build_batched(q, elem_off, cells_like(elem_off, cell_ratio))
         idx, x = sample_batched(f, sample_off, u, want_x=True)
+        ctx.plan = None
         ctx.forest = f
         ctx.save_for_backward(u, idx, scale, sample_off)
         ctx.v_dtype = v.dtype
@@ -34,6 +46,10 @@ class RTFSample(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_x):
+        if ctx.plan is not None:
+            (u,) = ctx.saved_tensors
+            g = ctx.plan.backward(u, grad_x.contiguous())
+            return g, None, None, None, None
         u, idx, scale, sample_off = ctx.saved_tensors
         g = backward(ctx.forest, u, idx, grad_x.contiguous().to(torch.float64), scale,
                      sample_off=sample_off)

@@ -23,7 +23,8 @@ class BatchedPlan:
     (passed from the host so that nothing is read back).
     """
 
-    def __init__(self, elem_off, cell_off, sample_off, n_total, m_total, S, want_x=True):
+    def __init__(self, elem_off, cell_off, sample_off, n_total, m_total, S, want_x=True,
+                 collapsed=False):
         dev = elem_off.device
         self.D = elem_off.numel() - 1
         self.elem_off, self.cell_off, self.sample_off = elem_off, cell_off, sample_off
@@ -39,9 +40,15 @@ class BatchedPlan:
         self.idx = torch.empty(self.S, dtype=torch.int32, device=dev)
         self.x = torch.empty(self.S, dtype=torch.float64, device=dev) if want_x else None
         self.desc = rtf_forest()
+        self.collapsed = collapsed
+        self.wide_ws = None
+        if collapsed:
+            self.wide_ws = torch.empty(L.rtf_wide_workspace_bytes(self.n), dtype=torch.uint8,
+                                       device=dev)
 
     def run(self, v, u, stream=None):
-        """Enqueue quantise + build + sample; returns (idx, x) views."""
+        """Enqueue quantise + build (+ collapsed records) + sample; returns
+        (idx, x) views."""
         L = lib()
         st = _stream(stream)
         _check(L.rtf_quantize_f32(_ptr(v), _ptr(self.elem_off), self.D, self.n, _ptr(self.q),
@@ -49,6 +56,9 @@ class BatchedPlan:
         _check(L.rtf_build_batched(_ptr(self.q), _ptr(self.elem_off), _ptr(self.cell_off),
                                    self.D, self.n, self.m, _ptr(self.ws), self.ws_bytes, st,
                                    ctypes.byref(self.desc)), "rtf_build_batched")
+        if self.collapsed:
+            _check(L.rtf_forest_widen(ctypes.byref(self.desc), _ptr(self.wide_ws),
+                                      self.wide_ws.numel(), st), "rtf_forest_widen")
         _check(L.rtf_sample_batched(ctypes.byref(self.desc), _ptr(self.sample_off), _ptr(u),
                                     self.S, _ptr(self.idx), _ptr(self.x), st),
                "rtf_sample_batched")
@@ -77,3 +87,35 @@ class BatchedPlan:
             raise RtfError(code, "rtf_check")
         if int(self.status.item()) & (1 << 6):
             raise RtfError(6, "rtf_quantize_f32")
+
+
+class DiffPlan(BatchedPlan):
+    """A BatchedPlan that also owns the adjoint's workspace and outputs, so
+    that RTFSample's forward and backward allocate nothing and read nothing
+    back: the whole differentiable step can be captured as one HIP graph.
+
+    The forward returns a view of the plan's position buffer, and the
+    backward the plan's gradient buffer: both are overwritten by the next
+    call through the same plan.
+    """
+
+    def __init__(self, elem_off, cell_off, sample_off, n_total, m_total, S, v_dtype=torch.float32,
+                 collapsed=False):
+        super().__init__(elem_off, cell_off, sample_off, n_total, m_total, S, want_x=True,
+                         collapsed=collapsed)
+        L = lib()
+        dev = elem_off.device
+        self.bws_bytes = L.rtf_backward_workspace_bytes(self.D, self.n)
+        self.bws = torch.empty(self.bws_bytes, dtype=torch.uint8, device=dev)
+        self.grad_w = torch.empty(self.n, dtype=torch.float64, device=dev)
+        self.grad_v = torch.empty(self.n, dtype=v_dtype, device=dev)
+
+    def backward(self, u, grad_x, stream=None):
+        """Enqueue rtf_backward for the last run(); returns grad_v (dL/dv in
+        the weights' dtype)."""
+        _check(lib().rtf_backward(ctypes.byref(self.desc), _ptr(self.sample_off), _ptr(u),
+                                  _ptr(self.idx), _ptr(grad_x), self.S, _ptr(self.scale),
+                                  _ptr(self.grad_w), _ptr(self.bws), self.bws_bytes,
+                                  _stream(stream)), "rtf_backward")
+        self.grad_v.copy_(self.grad_w)
+        return self.grad_v

@@ -1,4 +1,4 @@
-"""Autotuner for the guide-table size.
+"""Autotuner for the guide-table size and the descent form.
 
 The sampled indices do not depend on the number of guide cells m; only speed
 does.  The paper leaves m open ("as much memory as affordable, or
@@ -109,3 +109,38 @@ def best_cell_ratio(w, u, candidates=CANDIDATES, use_cache=True, reps=5, with_ti
         cache[key] = {"ratio": best, "ms": {str(k): v for k, v in times.items()}}
         store_cache(cache)
     return (best, {str(k): v for k, v in times.items()}) if with_times else best
+
+
+BATCH_CANDIDATES = tuple((r, c) for r in (0.125, 0.25, 0.5, 1.0) for c in (False, True))
+
+
+def best_batched(v, u, elem_off, sample_off, candidates=BATCH_CANDIDATES, use_cache=True,
+                 reps=5, key_extra=""):
+    """(ratio, collapsed, times) with the fastest quantise + build (+ collapse)
+    + sample of the batch: v float32 weights, u uint64 uniforms, elem_off and
+    sample_off int64 device offsets (D+1).  times maps "ratio|collapsed" to ms
+    ({} when the choice came from the environment or the cache)."""
+    forced = forced_ratio()
+    if forced is not None:
+        return forced, False, {}
+    from . import cells_like
+    from .plan import BatchedPlan
+    D = elem_off.numel() - 1
+    n, S = v.numel(), u.numel()
+    key = bucket_key(device_arch(), f"batched|D2^{int(round(math.log2(max(D, 1))))}{key_extra}",
+                     n, S)
+    cache = load_cache() if use_cache else {}
+    if key in cache:
+        return float(cache[key]["ratio"]), bool(cache[key]["collapsed"]), {}
+    times = {}
+    for r, c in candidates:
+        co = cells_like(elem_off, r)
+        plan = BatchedPlan(elem_off, co, sample_off, n, int(co[-1].item()), S, collapsed=c)
+        times[f"{r}|{int(c)}"] = _time_ms(lambda: plan.run(v, u), reps)
+        del plan
+    best = min(times, key=times.get)
+    r, c = best.split("|")
+    if use_cache:
+        cache[key] = {"ratio": float(r), "collapsed": bool(int(c)), "ms": times}
+        store_cache(cache)
+    return float(r), bool(int(c)), times

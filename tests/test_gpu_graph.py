@@ -85,3 +85,63 @@ def test_tuned_cell_ratio_keeps_indices(orc, tmp_path, monkeypatch):
     idx, x = rtf.sample(f, ud)
     i_ref, x_ref = orc.search(w, u)
     assert_samples(idx.cpu().numpy(), x.cpu().numpy(), i_ref, x_ref)
+
+
+def test_graph_captured_autograd_forward_backward(orc):
+    """RTFSample through a DiffPlan: the differentiable step (softplus, quantise,
+    build, sample, the adjoint of L = sum sin(7x)) captured as one graph; every
+    replay's dL/dz against the oracle's FP64 gradient (1e-4 of its norms)."""
+    import torch
+    import paper_1901_05423_amd as rtf
+    from paper_1901_05423_amd.plan import DiffPlan
+    note("graph autograd D=8 n=4096")
+    rng = np.random.default_rng(91)
+    D, n, per = 8, 4096, 1 << 15
+    z_h = rng.standard_normal((D, n)).astype(np.float32)
+    u_h = rng.integers(0, 2 ** 64, D * per, dtype=np.uint64)
+    eo = to_dev(np.arange(D + 1, dtype=np.int64) * n)
+    so = to_dev(np.arange(D + 1, dtype=np.int64) * per)
+    co = to_dev(np.arange(D + 1, dtype=np.int64) * (n // 4))
+    plan = DiffPlan(eo, co, so, D * n, D * (n // 4), D * per)
+    z = to_dev(z_h).requires_grad_(True)
+    u = to_dev(u_h)
+
+    def step():
+        v = torch.nn.functional.softplus(z).reshape(-1)
+        x = rtf.RTFSample.apply(v, u, plan)
+        # dL/dx of L = sum sin(7x), passed directly: no reduction kernel in
+        # the captured graph
+        x.backward(7.0 * torch.cos(7.0 * x.detach()))
+        return x
+
+    # eager warm-up on a side stream, then the capture
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            z.grad = None
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    z.grad = None
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        x_c = step()
+    sig = 1.0 / (1.0 + np.exp(-z_h.astype(np.float64)))
+    for rep in range(3):
+        z.grad.fill_(np.nan)
+        g.replay()
+        torch.cuda.synchronize()
+        gz = z.grad.detach().double().cpu().numpy()
+        x_h = x_c.detach().cpu().numpy()
+        v32 = torch.nn.functional.softplus(z.detach()).reshape(-1).cpu().numpy()
+        for d in (0, 3, 7):
+            q, sc = orc.quantize(v32[d * n:(d + 1) * n])
+            uu = u_h[d * per:(d + 1) * per]
+            i_ref, x_ref = orc.search(q, uu)
+            assert np.abs(x_h[d * per:(d + 1) * per] - x_ref).max() <= 1e-12, (rep, d)
+            ref = orc.grad(q, sc[0], uu, 7.0 * np.cos(7.0 * x_ref)) * sig[d]
+            err = gz[d] - ref
+            assert np.abs(err).max() <= 1e-4 * np.abs(ref).max(), (rep, d)
+            assert np.linalg.norm(err) <= 1e-4 * np.linalg.norm(ref), (rep, d)
+        _ = (z * 2).sum().item()  # eager work between replays
