@@ -52,11 +52,15 @@ def lib():
         _lib.oracle_levels.argtypes = [P, I64, I64, P]
         _lib.oracle_alg1.argtypes = [P, I64, I64, ctypes.c_uint64, P, P]
         _lib.oracle_grad.argtypes = [P, I64, ctypes.c_double, P, P, I64, P]
+        _lib.oracle_alias_build.argtypes = [P, I64, P, P, P]
+        _lib.oracle_alias_sample.argtypes = [P, P, I64, ctypes.c_uint64, P, I64, P]
         for f in ("oracle_quantize", "oracle_search", "oracle_linear_search",
-                  "oracle_forest", "oracle_levels", "oracle_alg1", "oracle_grad"):
+                  "oracle_forest", "oracle_levels", "oracle_alg1", "oracle_grad",
+                  "oracle_alias_build"):
             getattr(_lib, f).restype = ctypes.c_int
         _lib.oracle_prefix.restype = None
         _lib.oracle_descend.restype = None
+        _lib.oracle_alias_sample.restype = None
     return _lib
 
 
@@ -200,3 +204,41 @@ def grad(q, scale, u, g):
     if rc != ORC_OK:
         raise OracleError(rc)
     return out
+
+
+class Alias:
+    """An alias table (Sec. 2.6): per cell j the part thr[j] of the cell's
+    capacity W kept by item j, and the item alias[j] that takes the rest."""
+
+    def __init__(self, thr, alias, W):
+        self.thr, self.alias, self.W = thr, alias, int(W)
+
+
+def alias_build(w):
+    """Walker's alias table by Vose's two-worklist construction, in exact
+    integers (item mass w_i * n, cell capacity W = sum w)."""
+    w = _c(w, np.uint32)
+    n = w.size
+    thr = np.zeros(n, np.uint64)
+    alias = np.zeros(n, np.int32)
+    work = np.zeros(2 * n, np.int64)
+    rc = lib().oracle_alias_build(_p(w), n, _p(thr), _p(alias), _p(work))
+    if rc != ORC_OK:
+        raise OracleError(rc)
+    return Alias(thr, alias, int(w.astype(np.uint64).sum()))
+
+
+def alias_sample(t: Alias, u):
+    """Indices the alias table maps the uniforms u (uint64) to."""
+    u = _c(u, np.uint64)
+    idx = np.zeros(u.size, np.int32)
+    lib().oracle_alias_sample(_p(t.thr), _p(t.alias), t.thr.size, t.W, _p(u), u.size, _p(idx))
+    return idx
+
+
+def quadratic_error(p, counts, N):
+    """The quadratic error of Fig. convergence: the sum over the values i of
+    (p_i - c_i / N)^2, c_i the number of the N samples that realised i."""
+    p = np.asarray(p, np.float64)
+    c = np.asarray(counts, np.float64)
+    return float(np.sum((p - c / float(N)) ** 2))

@@ -524,3 +524,78 @@ int oracle_grad(const uint32_t *q, int64_t n, double scale, const uint64_t *u,
     free(Dv);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The Alias Method (Sec. 2.6 "The Alias Method", Fig. alias_map: Walker's  */
+/* table of cells holding at most two intervals, the cell's own and one     */
+/* alias), built by the two-worklist construction of Vose (IEEE TSE 1991)   */
+/* in exact integers.  The comparison mapping of the paper's quality study  */
+/* (Figs. results_sine64, 2d_zoom, convergence); it is not monotone.        */
+/*                                                                          */
+/* Units: item i carries a_i = w_i * n, a cell holds W = sum w, so the n    */
+/* cells hold exactly the total mass.  thr[j] in [0, W] is the part of cell */
+/* j kept by item j; the rest, W - thr[j], belongs to alias[j].             */
+/* Order (fixed so that any implementation can reproduce the table): the    */
+/* items with a_i < W ("small") and a_i >= W ("large") are pushed onto two  */
+/* stacks in increasing index order; each step pops the top of both, gives  */
+/* the small item's cell its remainder to the large item, and pushes the    */
+/* large item back onto the stack its remaining mass now belongs to.  With  */
+/* exact integers the stacks run empty together, or the large one is left   */
+/* holding items of mass exactly W (their cells keep all of it).            */
+/* work: 2n int64 entries of scratch.  Returns ORC_ERR_ZERO_TOTAL if W = 0. */
+/* ------------------------------------------------------------------------ */
+int oracle_alias_build(const uint32_t *w, int64_t n, uint64_t *thr, int32_t *alias,
+                       int64_t *work)
+{
+    if (n < 1)
+        return ORC_ERR_ARG;
+    uint64_t W = 0;
+    for (int64_t i = 0; i < n; ++i)
+        W += w[i];
+    if (W == 0)
+        return ORC_ERR_ZERO_TOTAL;
+    int64_t *small = work, *large = work + n;
+    int64_t ns = 0, nl = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        thr[i] = (uint64_t)w[i] * (uint64_t)n; /* the mass still to place */
+        alias[i] = (int32_t)i;
+        if (thr[i] < W)
+            small[ns++] = i;
+        else
+            large[nl++] = i;
+    }
+    while (ns > 0 && nl > 0) {
+        int64_t s = small[--ns], l = large[--nl];
+        alias[s] = (int32_t)l;                 /* thr[s] = a_s stays */
+        thr[l] -= W - thr[s];                  /* >= a_s >= 0 since a_l >= W */
+        if (thr[l] < W)
+            small[ns++] = l;
+        else
+            large[nl++] = l;
+    }
+    while (nl > 0) { /* mass exactly W: the cell is the item's own */
+        int64_t l = large[--nl];
+        thr[l] = W;
+        alias[l] = (int32_t)l;
+    }
+    if (ns > 0) /* impossible with exact sums */
+        return ORC_ERR_ARG;
+    return ORC_OK;
+}
+
+/* Sample the alias table: xi = u 2^-64 falls in cell j = floor(xi n) at
+ * relative position f = xi n - j; the item is j when f < thr[j] / W, else
+ * alias[j].  In integers: j:r = u * n (high:low 64 bits), f = r 2^-64, and
+ * f < thr/W  <=>  r W < thr 2^64  <=>  floor(r W / 2^64) < thr (thr is an
+ * integer), so the test is exact. */
+void oracle_alias_sample(const uint64_t *thr, const int32_t *alias, int64_t n, uint64_t W,
+                         const uint64_t *u, int64_t S, int32_t *idx)
+{
+    for (int64_t s = 0; s < S; ++s) {
+        u128 p = (u128)u[s] * (u128)(uint64_t)n;
+        int64_t j = (int64_t)(p >> 64);
+        uint64_t r = (uint64_t)p;
+        uint64_t t = (uint64_t)(((u128)r * (u128)W) >> 64);
+        idx[s] = t < thr[j] ? (int32_t)j : alias[j];
+    }
+}
