@@ -50,12 +50,13 @@ def lib():
         _lib.oracle_forest.argtypes = [P, P, P, ctypes.c_int32, P, P, P, P]
         _lib.oracle_descend.argtypes = [P, P, P, I64, I64, I64, P, I64, P]
         _lib.oracle_levels.argtypes = [P, I64, I64, P]
+        _lib.oracle_balance.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
         _lib.oracle_alg1.argtypes = [P, I64, I64, ctypes.c_uint64, P, P]
         _lib.oracle_grad.argtypes = [P, I64, ctypes.c_double, P, P, I64, P]
         _lib.oracle_alias_build.argtypes = [P, I64, P, P, P]
         _lib.oracle_alias_sample.argtypes = [P, P, I64, ctypes.c_uint64, P, I64, P]
         for f in ("oracle_quantize", "oracle_search", "oracle_linear_search",
-                  "oracle_forest", "oracle_levels", "oracle_alg1", "oracle_grad",
+                  "oracle_forest", "oracle_levels", "oracle_alg1", "oracle_grad", "oracle_balance",
                   "oracle_alias_build"):
             getattr(_lib, f).restype = ctypes.c_int
         _lib.oracle_prefix.restype = None
@@ -160,6 +161,20 @@ def forest(w, m=None, elem_off=None, cell_off=None):
     if rc != ORC_OK:
         raise OracleError(rc)
     return Forest(key, child, table, W, elem_off, cell_off)
+
+
+def balance(f: Forest):
+    """The depth fallback (Sec. 3): a copy of f whose degenerate cell trees
+    (a positive-weight leaf more than 2 ceil(log2 c) internal nodes deep in a
+    cell of c leaves) are replaced by balanced ones; returns (forest, rebuilt)."""
+    child = f.child.copy()
+    rebuilt = np.zeros(1, np.int64)
+    D = f.elem_off.size - 1
+    rc = lib().oracle_balance(_p(f.elem_off), _p(f.cell_off), D, _p(f.key), _p(child),
+                              _p(f.table), _p(rebuilt))
+    if rc != ORC_OK:
+        raise OracleError(rc)
+    return Forest(f.key, child, f.table, f.W, f.elem_off, f.cell_off), int(rebuilt[0])
 
 
 def descend(f: Forest, u, d=0):

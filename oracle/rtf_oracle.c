@@ -21,7 +21,8 @@
  *
  * Pins (tests/): brute-force linear search, monotonicity, closed forms for
  * equal weights and regular grids, the worked forest figure, the printed
- * sine^2 histograms, Algorithm 1 under random schedules, finite differences.
+ * sine^2 histograms, Algorithm 1 under random schedules, finite differences,
+ * a hand-built balanced tree for the depth fallback.
  * No function here is "parity unpinned".
  */
 #include <math.h>
@@ -354,6 +355,79 @@ void oracle_descend(const uint64_t *key, const int32_t *child,
                                 : child[2 * (int64_t)j + 1];
         idx[s] = (int32_t)((int64_t)(~j) - eo);
     }
+}
+
+/*
+ * Depth fallback (Sec. 3: a degenerate tree would cost O(n) per search, so a
+ * fallback builds a structure with logarithmic depth when one is detected).
+ * Reading: the tree of a guide cell holding c lower bounds (leaves a..a+c-1,
+ * hung as child 1 of node a) is degenerate when some leaf with positive
+ * weight lies more than 2 ceil(log2 c) internal nodes below that tree's root,
+ * i.e. when Alg. 2, entering at node a, visits more than 1 + 2 ceil(log2 c)
+ * nodes for it.  Such a tree is replaced by the balanced one over the same
+ * leaves: split(lo, hi) is leaf ~lo when lo == hi, else node mid with
+ * mid = ceil((lo + hi) / 2), left subtree split(lo, mid-1) and right
+ * subtree split(mid, hi).  Every node keeps its key U_j and still splits
+ * between leaf j-1 and j, so any search gives the index binary search gives.
+ * Works in place on a forest from oracle_forest; *rebuilt receives the number
+ * of cells replaced.
+ */
+static int ceil_log2(int64_t c)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < c)
+        ++l;
+    return l;
+}
+
+static int32_t balanced_split(int32_t *child, int64_t lo, int64_t hi)
+{
+    if (lo == hi)
+        return ~(int32_t)lo;
+    int64_t mid = (lo + hi + 1) / 2;
+    child[2 * mid + 0] = balanced_split(child, lo, mid - 1);
+    child[2 * mid + 1] = balanced_split(child, mid, hi);
+    return (int32_t)mid;
+}
+
+int oracle_balance(const int64_t *elem_off, const int64_t *cell_off, int32_t D,
+                   const uint64_t *key, int32_t *child, const int32_t *table,
+                   int64_t *rebuilt)
+{
+    int64_t count = 0;
+    for (int32_t d = 0; d < D; ++d) {
+        int64_t end = elem_off[d + 1];
+        int64_t co = cell_off[d], m = cell_off[d + 1] - co;
+        for (int64_t g = 0; g < m; ++g) {
+            int64_t a = table[co + g];
+            if (a < 0)
+                continue; /* covered by one interval: no tree */
+            int64_t b = a; /* last leaf whose lower bound lies in cell g */
+            while (b + 1 < end && key[b + 1] != UINT64_MAX && cell_of(key[b + 1], m) == g)
+                ++b;
+            int64_t c = b - a + 1;
+            int64_t deepest = 0; /* nodes Alg. 2 visits from node a */
+            for (int64_t i = a; i <= b; ++i) {
+                int live = (i + 1 == end) || key[i + 1] == UINT64_MAX || key[i + 1] != key[i];
+                if (!live)
+                    continue; /* zero weight: no uniform reaches it */
+                int64_t visits = 0;
+                int32_t j = (int32_t)a;
+                while (j >= 0) {
+                    ++visits;
+                    j = key[i] < key[j] ? child[2 * (int64_t)j] : child[2 * (int64_t)j + 1];
+                }
+                if (visits > deepest)
+                    deepest = visits;
+            }
+            if (deepest - 1 > 2 * ceil_log2(c)) {
+                child[2 * a + 1] = balanced_split(child, a, b);
+                ++count;
+            }
+        }
+    }
+    *rebuilt = count;
+    return ORC_OK;
 }
 
 /* Levels of all boundaries of one distribution (for tests): lvl[b] for
