@@ -263,6 +263,31 @@ rtf_status rtf_backward(const rtf_forest *f, const int64_t *sample_off,
                         double *grad_w, void *ws, size_t ws_bytes,
                         hipStream_t stream);
 
+/*
+ * rtf_backward with its scratch in a fixed device array of the library
+ * instead of a caller workspace.  For callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the call allocates and frees nothing, on the device or
+ * through any allocating library routine.  Arguments, results and errors are
+ * those of rtf_backward, less the workspace, plus:
+ *   RTF_ERR_SIZE  f->n_total > RTF_BACKWARD_STATIC_MAX_N or
+ *                 f->D > RTF_BACKWARD_STATIC_MAX_D (nothing is enqueued)
+ *   RTF_ERR_HIP   the array's device address could not be obtained
+ * Each GPU holds one copy of the array (about 16.5 MiB at these limits) from
+ * the first call on it until the process ends.  Every call on one GPU uses
+ * that same copy, and the pass clears what it accumulates before use, so
+ * calls in stream order are independent; calls that overlap on one GPU (on
+ * different streams, or from several threads without ordering) race on it
+ * and give undefined results.
+ */
+#define RTF_BACKWARD_STATIC_MAX_N (1 << 20)
+#define RTF_BACKWARD_STATIC_MAX_D (1 << 16)
+rtf_status rtf_backward_static(const rtf_forest *f, const int64_t *sample_off,
+                               const uint64_t *u, const int32_t *idx,
+                               const double *grad_x, int64_t S,
+                               const double *scale, double *grad_w,
+                               hipStream_t stream);
+
 /* ---- inspection --------------------------------------------------------- */
 
 /* Synchronise the stream and return the first error recorded in the forest's

@@ -76,6 +76,7 @@ SIGNATURES = {
     "rtf_quantize_f32": (ctypes.c_int, [_P, _P, _I32, _I64, _P, _P, _P, _P]),
     "rtf_backward_workspace_bytes": (_SZ, [_I32, _I64]),
     "rtf_backward": (ctypes.c_int, [_FP, _P, _P, _P, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "rtf_backward_static": (ctypes.c_int, [_FP, _P, _P, _P, _P, _I64, _P, _P, _P]),
     "rtf_check": (ctypes.c_int, [_FP, _P]),
     "rtf_forest_depth": (ctypes.c_int, [_FP, _P, _P]),
     "rtf_forest_export": (ctypes.c_int, [_FP, _P, _P, _P, _P]),
@@ -361,6 +362,19 @@ def backward(f: Forest, u, idx, grad_x, scale, sample_off=None, ws=None, stream=
     _check(lib().rtf_backward(ctypes.byref(f.desc), _ptr(sample_off), _ptr(u), _ptr(idx),
                               _ptr(grad_x), u.numel(), _ptr(scale), _ptr(grad_w), _ptr(ws), nb,
                               _stream(stream)), "rtf_backward")
+    return grad_w
+
+
+def backward_static(f: Forest, u, idx, grad_x, scale, sample_off=None, out=None, stream=None):
+    """rtf_backward_static: backward() with the library's fixed device scratch
+    (no workspace; n_total <= 2^20 and D <= 2^16).  `out` is an optional
+    preallocated float64[n_total] result, so that the call allocates nothing."""
+    torch = _torch()
+    grad_w = out if out is not None else torch.empty(f.n_total, dtype=torch.float64,
+                                                     device=u.device)
+    _check(lib().rtf_backward_static(ctypes.byref(f.desc), _ptr(sample_off), _ptr(u), _ptr(idx),
+                                     _ptr(grad_x), u.numel(), _ptr(scale), _ptr(grad_w),
+                                     _stream(stream)), "rtf_backward_static")
     return grad_w
 
 

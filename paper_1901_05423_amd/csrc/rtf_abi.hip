@@ -11,8 +11,6 @@ namespace {
 
 constexpr int64_t MAX_I32 = 2147483647;
 
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
 // Workspace layout of a forest of D distributions, n_total leaves, m_total cells.
 struct Layout {
     size_t status, nodes, cells, dists, eoff, coff, tsum, tpre, dloc, tdist, dcnt, ditems, runs,
@@ -130,33 +128,24 @@ bool sample_args_ok(const uint64_t *u, int64_t S, const int32_t *idx, const doub
     return u && idx && aligned(u, 8) && aligned(idx, 4) && (!x || aligned(x, 8));
 }
 
-// Backward scratch layout: B[n], D[n], A[D], head[nch], carry[nch], link[nch].
-size_t backward_layout(int32_t D, int64_t n, char *base, BackwardScratch *w) {
-    const int64_t nch = backward_chunks(n);
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        const size_t at = o;
-        o = align256(o + bytes);
-        return base + at;
-    };
-    char *B = take(sizeof(double) * (size_t)n);
-    char *Dv = take(sizeof(double) * (size_t)n);
-    char *A = take(sizeof(double) * (size_t)D);
-    char *head = take(sizeof(double) * (size_t)nch);
-    char *carry = take(sizeof(double) * (size_t)nch);
-    char *link = take(sizeof(int32_t) * (size_t)nch);
-    if (w) {
-        w->B = reinterpret_cast<double *>(B);
-        w->Dv = reinterpret_cast<double *>(Dv);
-        w->A = reinterpret_cast<double *>(A);
-        w->head = reinterpret_cast<double *>(head);
-        w->carry = reinterpret_cast<double *>(carry);
-        w->link = reinterpret_cast<int32_t *>(link);
-    }
-    return o;
-}
 
 }  // namespace
+
+// The checks and launches of a backward pass whose scratch is w (shared by
+// rtf_backward and the static-scratch variant).
+rtf_status rtf::backward_enqueue(const rtf_forest *f, const int64_t *sample_off, const uint64_t *u,
+                                 const int32_t *idx, const double *grad_x, int64_t S,
+                                 const double *scale, double *grad_w, const BackwardScratch &w,
+                                 hipStream_t stream) {
+    if (!forest_ok(f) || !scale || !grad_w || S < 0) return RTF_ERR_INVALID_ARG;
+    if (S > 0 && (!u || !idx || !grad_x)) return RTF_ERR_INVALID_ARG;
+    if (f->D > 1 && !sample_off) return RTF_ERR_INVALID_ARG;
+    if (!aligned(grad_w, 8) || !aligned(scale, 8)) return RTF_ERR_INVALID_ARG;
+    return from_hip(launch_backward(static_cast<const Node *>(f->nodes),
+                                    static_cast<const Dist *>(f->dists), f->elem_off, f->D,
+                                    f->n_total, f->D > 1 ? sample_off : nullptr, u, idx, grad_x,
+                                    S, scale, grad_w, w, stream));
+}
 
 extern "C" {
 
@@ -298,18 +287,11 @@ size_t rtf_backward_workspace_bytes(int32_t D, int64_t n_total) {
 rtf_status rtf_backward(const rtf_forest *f, const int64_t *sample_off, const uint64_t *u,
                         const int32_t *idx, const double *grad_x, int64_t S, const double *scale,
                         double *grad_w, void *ws, size_t ws_bytes, hipStream_t stream) {
-    if (!forest_ok(f) || !scale || !grad_w || !ws || S < 0) return RTF_ERR_INVALID_ARG;
-    if (S > 0 && (!u || !idx || !grad_x)) return RTF_ERR_INVALID_ARG;
-    if (f->D > 1 && !sample_off) return RTF_ERR_INVALID_ARG;
-    if (!aligned(ws, 256) || !aligned(grad_w, 8) || !aligned(scale, 8))
-        return RTF_ERR_INVALID_ARG;
+    if (!forest_ok(f) || !ws || !aligned(ws, 256)) return RTF_ERR_INVALID_ARG;
     if (ws_bytes < rtf_backward_workspace_bytes(f->D, f->n_total)) return RTF_ERR_WORKSPACE;
     BackwardScratch w;
     backward_layout(f->D, f->n_total, static_cast<char *>(ws), &w);
-    return from_hip(launch_backward(static_cast<const Node *>(f->nodes),
-                                    static_cast<const Dist *>(f->dists), f->elem_off, f->D,
-                                    f->n_total, f->D > 1 ? sample_off : nullptr, u, idx, grad_x,
-                                    S, scale, grad_w, w, stream));
+    return backward_enqueue(f, sample_off, u, idx, grad_x, S, scale, grad_w, w, stream);
 }
 
 rtf_status rtf_check(const rtf_forest *f, hipStream_t stream) {

@@ -251,13 +251,40 @@ hipError_t launch_quantize(const float *v, const int64_t *elem_off, int32_t D,
 // distribution A, per chunk of BACKWARD_CHUNK elements the combining pass's
 // head sum, link bits and carry.
 constexpr int64_t BACKWARD_CHUNK = 4096;
-__host__ __device__ inline int64_t backward_chunks(int64_t n_total) {
+__host__ __device__ constexpr int64_t backward_chunks(int64_t n_total) {
     return (n_total + BACKWARD_CHUNK - 1) / BACKWARD_CHUNK;
 }
 struct BackwardScratch {
     double *B, *Dv, *A, *head, *carry;
     int32_t *link;
 };
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Backward scratch layout from base: B[n], D[n], A[D], head[nch], carry[nch],
+// link[nch], each 256-byte aligned; returns the bytes it spans (w may be null).
+constexpr size_t backward_layout(int32_t D, int64_t n, char *base, BackwardScratch *w) {
+    const int64_t nch = backward_chunks(n);
+    size_t off[7] = {};
+    const size_t bytes[6] = {sizeof(double) * (size_t)n,   sizeof(double) * (size_t)n,
+                             sizeof(double) * (size_t)D,   sizeof(double) * (size_t)nch,
+                             sizeof(double) * (size_t)nch, sizeof(int32_t) * (size_t)nch};
+    for (int k = 0; k < 6; ++k) off[k + 1] = align256(off[k] + bytes[k]);
+    if (w) {
+        w->B = reinterpret_cast<double *>(base + off[0]);
+        w->Dv = reinterpret_cast<double *>(base + off[1]);
+        w->A = reinterpret_cast<double *>(base + off[2]);
+        w->head = reinterpret_cast<double *>(base + off[3]);
+        w->carry = reinterpret_cast<double *>(base + off[4]);
+        w->link = reinterpret_cast<int32_t *>(base + off[5]);
+    }
+    return off[6];
+}
+// Argument checks and launches of a backward pass over scratch w (rtf_abi.hip).
+rtf_status backward_enqueue(const rtf_forest *f, const int64_t *sample_off, const uint64_t *u,
+                            const int32_t *idx, const double *grad_x, int64_t S,
+                            const double *scale, double *grad_w, const BackwardScratch &w,
+                            hipStream_t stream);
 hipError_t launch_backward(const Node *nodes, const Dist *dists, const int64_t *elem_off,
                            int32_t D, int64_t n_total, const int64_t *sample_off,
                            const uint64_t *u, const int32_t *idx, const double *gx, int64_t S,

@@ -90,6 +90,18 @@ def test_argument_errors_before_launch(L):
     assert r == rtf.RTF_ERR_INVALID_ARG  # out_rc not 8-byte aligned
     r = L.rtf_sample_2d(ctypes.byref(f2), fake, 4, fake, P(0x100008), None)
     assert r == rtf.RTF_ERR_INVALID_ARG  # out_xy not 16-byte aligned
+    # the static-scratch backward rejects sizes past its array before any
+    # device call
+    big = rtf.rtf_forest(D=1, tile=2048, n_total=(1 << 20) + 1, m_total=10, nodes=0x100000,
+                         cells=0x100000, dists=0x100000, status=0x100000)
+    r = L.rtf_backward_static(ctypes.byref(big), None, None, None, None, 0, fake, fake, None)
+    assert r == rtf.RTF_ERR_SIZE
+    many = rtf.rtf_forest(D=(1 << 16) + 1, tile=2048, n_total=1 << 20, m_total=1 << 20,
+                          nodes=0x100000, cells=0x100000, dists=0x100000, status=0x100000)
+    r = L.rtf_backward_static(ctypes.byref(many), fake, None, None, None, 0, fake, fake, None)
+    assert r == rtf.RTF_ERR_SIZE
+    assert L.rtf_backward_static(None, None, None, None, None, 0, fake, fake, None) == \
+        rtf.RTF_ERR_INVALID_ARG
     for c in range(7):
         assert L.rtf_status_string(c).decode().startswith("RTF_")
 
