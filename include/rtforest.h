@@ -177,6 +177,34 @@ size_t rtf_wide_workspace_bytes(int64_t n_total);
  */
 rtf_status rtf_forest_widen(rtf_forest *f, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- depth fallback (Sec. 3) ------------------------------------------- */
+
+/* Bytes of workspace for rtf_forest_balance of a forest with m_total guide
+ * cells; 0 if out of range. */
+size_t rtf_balance_workspace_bytes(int64_t m_total);
+
+/*
+ * The fallback of Sec. 3 for degenerate trees: the tree of a guide cell
+ * holding c lower bounds (leaves a..a+c-1, child 1 of node a) is replaced
+ * when a leaf with positive weight lies more than 2 ceil(log2 c) internal
+ * nodes deep in it, by the balanced tree over the same leaves (the range
+ * [lo, hi] splits at node ceil((lo + hi) / 2)).  Keys and guide entries stay,
+ * so every search gives the same index as before; the cell record's aux
+ * follows the new root.  With 64-bit keys a search never exceeds
+ * 68 - floor(log2 m) reads (rtf_forest_depth), but a cell of geometrically
+ * falling weights forms a comb as deep as its leaf count up to that bound;
+ * after this call such a cell costs ceil(log2 c) + 2 reads.
+ *   f          a built forest; its `wide` field is cleared (call
+ *              rtf_forest_widen afterwards to collapse the new trees)
+ *   ws         rtf_balance_workspace_bytes(f->m_total) bytes, 256-byte
+ *              aligned (per-cell scratch, free after the call's kernels)
+ *   h_rebuilt  host pointer receiving the number of cells rebuilt, or NULL;
+ *              when given, the call synchronises the stream
+ * Asynchronous otherwise, after the build in stream order.
+ */
+rtf_status rtf_forest_balance(rtf_forest *f, void *ws, size_t ws_bytes, int64_t *h_rebuilt,
+                              hipStream_t stream);
+
 /* ---- sampling (Alg. 2, Sec. 5) ---------------------------------------- */
 
 /*

@@ -68,6 +68,8 @@ SIGNATURES = {
     "rtf_build_batched": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I64, _P, _SZ, _P, _FP]),
     "rtf_wide_workspace_bytes": (_SZ, [_I64]),
     "rtf_forest_widen": (ctypes.c_int, [_FP, _P, _SZ, _P]),
+    "rtf_balance_workspace_bytes": (_SZ, [_I64]),
+    "rtf_forest_balance": (ctypes.c_int, [_FP, _P, _SZ, _P, _P]),
     "rtf_sample": (ctypes.c_int, [_FP, _P, _I64, _P, _P, _P]),
     "rtf_sample_batched": (ctypes.c_int, [_FP, _P, _P, _I64, _P, _P, _P]),
     "rtf_sample_2d": (ctypes.c_int, [_FP, _P, _I64, _P, _P, _P]),
@@ -164,6 +166,22 @@ class Forest:
                "rtf_forest_widen")
         self.wide_ws = ws
         return self
+
+    def balance(self, ws=None, stream=None) -> int:
+        """The depth fallback (rtf_forest_balance): degenerate cell trees are
+        replaced by balanced ones; returns the number of cells rebuilt
+        (synchronises).  Collapsed records are dropped (widen() again)."""
+        nb = lib().rtf_balance_workspace_bytes(self.m_total)
+        if nb == 0:
+            raise RtfError(RTF_ERR_SIZE, "rtf_balance_workspace_bytes")
+        if ws is None or ws.numel() < nb:
+            ws = _workspace(nb, self.device)
+        count = ctypes.c_int64(0)
+        _check(lib().rtf_forest_balance(ctypes.byref(self.desc), _ptr(ws), nb,
+                                        ctypes.byref(count), _stream(stream)),
+               "rtf_forest_balance")
+        self.wide_ws = None
+        return int(count.value)
 
     def wide_view(self):
         """Device view of the collapsed records: int64 [n_total, 8] (k, kc0,

@@ -193,6 +193,34 @@ rtf_status rtf_forest_widen(rtf_forest *f, void *ws, size_t ws_bytes, hipStream_
     return RTF_OK;
 }
 
+size_t rtf_balance_workspace_bytes(int64_t m_total) {
+    if (m_total < 1 || m_total > MAX_I32) return 0;
+    return 2 * align256(sizeof(int32_t) * (size_t)m_total);
+}
+
+rtf_status rtf_forest_balance(rtf_forest *f, void *ws, size_t ws_bytes, int64_t *h_rebuilt,
+                              hipStream_t stream) {
+    if (!forest_ok(f) || !ws || !aligned(ws, 256)) return RTF_ERR_INVALID_ARG;
+    if (ws_bytes < rtf_balance_workspace_bytes(f->m_total)) return RTF_ERR_WORKSPACE;
+    int32_t *deep = static_cast<int32_t *>(ws);
+    int32_t *last = reinterpret_cast<int32_t *>(static_cast<char *>(ws) +
+                                                align256(sizeof(int32_t) * (size_t)f->m_total));
+    uint32_t *count = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(f->status) +
+                                                   STATUS_BALANCE_OFFSET);
+    if (launch_balance(static_cast<Node *>(f->nodes), static_cast<Cell *>(f->cells),
+                       static_cast<const Dist *>(f->dists), f->elem_off, f->D, f->n_total,
+                       f->m_total, deep, last, count, stream) != hipSuccess)
+        return RTF_ERR_HIP;
+    f->wide = nullptr;  // collapsed records, if any, describe the old trees
+    if (h_rebuilt) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return RTF_ERR_HIP;
+        uint32_t v = 0;
+        if (hipMemcpy(&v, count, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return RTF_ERR_HIP;
+        *h_rebuilt = (int64_t)v;
+    }
+    return RTF_OK;
+}
+
 rtf_status rtf_forest_depth(const rtf_forest *f, int32_t *h_depth, hipStream_t stream) {
     if (!forest_ok(f) || !h_depth) return RTF_ERR_INVALID_ARG;
     uint32_t *word = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(f->status) +

@@ -1351,6 +1351,144 @@ hipError_t launch_depth(const Node *nodes, const Cell *cells, const Dist *dists,
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Depth fallback (Sec. 3: a degenerate tree is replaced by a structure of
+// logarithmic depth).  The tree of a cell holding c lower bounds (leaves
+// a..b, hung as child 1 of node a) is replaced when a leaf with positive
+// weight lies more than 2 ceil(log2 c) internal nodes deep in it, by the
+// balanced tree that splits [lo, hi] at mid = ceil((lo + hi) / 2).  Keys and
+// guide entries stay, so every search still returns the binary-search index.
+//   k_bal_clear    per cell: deepest search 0, last leaf -1
+//   k_bal_measure  per leaf: the cell's last leaf (atomic max of the index);
+//                  for a leaf with positive weight, the nodes Alg. 2 visits
+//                  from node a down to it (atomic max)
+//   k_bal_rebuild  per node of a degenerate cell: its children in the
+//                  balanced tree, found by descending the implicit splits
+//                  from [a, b] (log2 c steps); node a takes the new root as
+//                  child 1, and so does the cell record when c > CELL_BOUNDS
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WT) void k_bal_clear(int32_t *deep, int32_t *last, int64_t m,
+                                                 uint32_t *count) {
+    const int64_t g = (int64_t)blockIdx.x * WT + threadIdx.x;
+    if (g < m) {
+        deep[g] = 0;
+        last[g] = -1;
+    }
+    if (g == 0) *count = 0u;
+}
+
+// The distribution of element i of a block that spans distributions
+// [dlo, dhi] (found once per block by two wave-wide searches).
+template <bool BATCHED>
+__device__ inline void block_dists(const int64_t *eoff, int32_t D, int64_t n, int64_t i0,
+                                   int32_t *s_d, int32_t &dlo, int32_t &dhi) {
+    dlo = dhi = 0;
+    if (!BATCHED) return;
+    const int w = threadIdx.x >> 6;
+    if (w < 2) {
+        const int64_t il = i0 + WT - 1 < n ? i0 + WT - 1 : n - 1;
+        const int32_t d = wave_upper_bound(eoff, D, w == 0 ? i0 : il) - 1;
+        if ((threadIdx.x & 63) == 0) s_d[w] = d;
+    }
+    __syncthreads();
+    dlo = s_d[0];
+    dhi = s_d[1];
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(WT) void k_bal_measure(const Node *__restrict__ nodes,
+                                                   const Cell *__restrict__ cells,
+                                                   const Dist *__restrict__ dists,
+                                                   const int64_t *__restrict__ eoff, int32_t D,
+                                                   int64_t n, int32_t *deep, int32_t *last) {
+    __shared__ int32_t s_d[2];
+    const int64_t i0 = (int64_t)blockIdx.x * WT;
+    const int64_t i = i0 + threadIdx.x;
+    int32_t dlo, dhi;
+    block_dists<BATCHED>(eoff, D, n, i0, s_d, dlo, dhi);
+    if (i >= n) return;
+    const int32_t d = (!BATCHED || dlo == dhi) ? dlo : find_segment_in(eoff, dlo, dhi + 1, i);
+    const Dist P = dists[d];
+    const uint64_t key = nodes[i].key;
+    if ((P.flags & DIST_ZERO) || key == KEY_END) return;  // no tree holds this leaf
+    const int64_t g = cell_of_key(key, P);
+    atomicMax(last + g, (int32_t)i);
+    const uint64_t next = i + 1 < P.eo + P.n ? nodes[i + 1].key : KEY_END;
+    if (next == key && next != KEY_END) return;  // zero weight: no uniform reaches it
+    int32_t j = cells[g].ref;  // node a: the leaf's lower bound lies in g
+    int32_t visits = 0;
+    for (int64_t guard = 0; j >= 0 && guard <= n; ++guard) {
+        const Node nd = nodes[j];
+        j = key < nd.key ? nd.c0 : nd.c1;
+        ++visits;
+    }
+    atomicMax(deep + g, visits);
+}
+
+__device__ inline int ceil_log2_i64(int64_t c) { return c <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)(c - 1)); }
+
+// reference to the balanced subtree over leaves [lo, hi]
+__device__ inline int32_t split_ref(int64_t lo, int64_t hi) {
+    return lo == hi ? ~(int32_t)lo : (int32_t)((lo + hi + 1) / 2);
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(WT) void k_bal_rebuild(Node *__restrict__ nodes, Cell *__restrict__ cells,
+                                                   const Dist *__restrict__ dists,
+                                                   const int64_t *__restrict__ eoff, int32_t D,
+                                                   int64_t n, const int32_t *__restrict__ deep,
+                                                   const int32_t *__restrict__ last,
+                                                   uint32_t *count) {
+    __shared__ int32_t s_d[2];
+    const int64_t j0 = (int64_t)blockIdx.x * WT;
+    const int64_t j = j0 + threadIdx.x;
+    int32_t dlo, dhi;
+    block_dists<BATCHED>(eoff, D, n, j0, s_d, dlo, dhi);
+    if (j >= n) return;
+    const int32_t d = (!BATCHED || dlo == dhi) ? dlo : find_segment_in(eoff, dlo, dhi + 1, j);
+    const Dist P = dists[d];
+    const uint64_t key = nodes[j].key;
+    if ((P.flags & DIST_ZERO) || key == KEY_END) return;
+    const int64_t g = cell_of_key(key, P);
+    const int64_t a = cells[g].ref, b = last[g], c = b - a + 1;
+    if (deep[g] - 1 <= 2 * ceil_log2_i64(c)) return;  // not degenerate
+    if (j == a) {
+        const int32_t root = split_ref(a, b);
+        nodes[j].c1 = root;
+        if (c > CELL_BOUNDS) cells[g].aux = root;
+        atomicAdd(count, 1u);
+        return;
+    }
+    int64_t lo = a, hi = b, mid = (lo + hi + 1) / 2;
+    while (mid != j) {  // j in (a, b]: every range on the way holds it
+        if (j < mid) hi = mid - 1;
+        else lo = mid;
+        mid = (lo + hi + 1) / 2;
+    }
+    nodes[j].c0 = split_ref(lo, mid - 1);
+    nodes[j].c1 = split_ref(mid, hi);
+}
+
+hipError_t launch_balance(Node *nodes, Cell *cells, const Dist *dists, const int64_t *elem_off,
+                          int32_t D, int64_t n_total, int64_t m_total, int32_t *deep,
+                          int32_t *last, uint32_t *count, hipStream_t st) {
+    hipLaunchKernelGGL(k_bal_clear, dim3((unsigned)((m_total + WT - 1) / WT)), dim3(WT), 0, st,
+                       deep, last, m_total, count);
+    const dim3 g((unsigned)((n_total + WT - 1) / WT)), b(WT);
+    if (D > 1) {
+        hipLaunchKernelGGL(k_bal_measure<true>, g, b, 0, st, nodes, cells, dists, elem_off, D,
+                           n_total, deep, last);
+        hipLaunchKernelGGL(k_bal_rebuild<true>, g, b, 0, st, nodes, cells, dists, elem_off, D,
+                           n_total, deep, last, count);
+    } else {
+        hipLaunchKernelGGL(k_bal_measure<false>, g, b, 0, st, nodes, cells, dists, elem_off, D,
+                           n_total, deep, last);
+        hipLaunchKernelGGL(k_bal_rebuild<false>, g, b, 0, st, nodes, cells, dists, elem_off, D,
+                           n_total, deep, last, count);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
     const bool vec = (reinterpret_cast<uintptr_t>(a.w) & 15) == 0;
     const dim3 grid((unsigned)a.ntiles);

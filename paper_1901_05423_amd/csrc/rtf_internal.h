@@ -244,6 +244,11 @@ hipError_t launch_depth(const Node *nodes, const Cell *cells, const Dist *dists,
                         hipStream_t st);
 // the depth word of the status block
 constexpr int STATUS_DEPTH_OFFSET = 128;
+// the count of cells the depth fallback rebuilt, in the status block
+constexpr int STATUS_BALANCE_OFFSET = 136;
+hipError_t launch_balance(Node *nodes, Cell *cells, const Dist *dists, const int64_t *elem_off,
+                          int32_t D, int64_t n_total, int64_t m_total, int32_t *deep,
+                          int32_t *last, uint32_t *count, hipStream_t st);
 hipError_t launch_quantize(const float *v, const int64_t *elem_off, int32_t D,
                            int64_t n_total, uint32_t *out, double *scale,
                            uint32_t *status, hipStream_t st);
