@@ -84,11 +84,13 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--profile", action="store_true",
                    help="few steps, no baselines (for rocprofv3 runs)")
-    p.add_argument("--config", choices=["h24", "c3", "c4", "c5", "table1", "grad1"],
+    p.add_argument("--config", choices=["h24", "c3", "c4", "c5", "table1", "grad1", "quality"],
                    default="h24",
                    help="h24: the benchmark line; c3/c4/c5: the 2D map, the uneven batch and "
                         "the differentiable workload; table1: load counts and speed on the "
-                        "paper's high-dynamic-range densities (extra measurements)")
+                        "paper's high-dynamic-range densities; quality: the quadratic error of "
+                        "Hammersley points mapped by the inverse and by the Alias Method on the "
+                        "2D map (extra measurements)")
     return p.parse_args()
 
 
@@ -267,7 +269,7 @@ def main():
         sys.exit(2)
     if args.config != "h24":
         {"c3": run_c3, "c4": run_c4, "c5": run_c5, "table1": run_table1,
-         "grad1": run_grad1}[args.config](args)
+         "grad1": run_grad1, "quality": run_quality}[args.config](args)
         return
     import ctypes
     import torch
@@ -827,6 +829,75 @@ def run_c3(args):
                  sample_only_pairs_s=pairs / (t_sample * 1e-3),
                  sample_only_pairs_s_collapsed=pairs / (t_sample_w * 1e-3),
                  row_lookup_loads=row_loads)
+    print(json.dumps(res), flush=True)
+
+
+def run_quality(args):
+    """The quality study of Figs. 2d_zoom and convergence on the C3 map: the
+    2D Hammersley set of N = 2^14 .. 2^26 points mapped to pixels by the
+    inverse (marginal then row, through the forest) and by the Alias Method
+    (marginal and row alias tables); e = sum over pixels (p - c / N)^2 with p
+    the exact probability of the quantised map and c the pixel's count.  Also
+    the sampling rate of both mappings at N = 2^26."""
+    import torch
+    import paper_1901_05423_amd as rtf
+    from paper_1901_05423_amd import workloads as wl
+    r = wl.rng(wl.C3_MAP_2D)
+    img, marg = wl.map_2d(r)
+    R, C = img.shape
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(np.concatenate([marg, img.ravel()])).to(dev)
+    eo = torch.from_numpy(np.concatenate([[0, R], R + C * np.arange(1, R + 1)]).astype(np.int64)).to(dev)
+    q, _ = rtf.quantize(v, eo)
+    f = rtf.build_batched(q, eo, rtf.cells_like(eo, 0.25))
+    t = rtf.alias_build(q, eo)
+    f.check()
+    t.export()  # raises on a recorded error
+    qm = q[:R].to(torch.float64)
+    rows = q[R:].to(torch.float64).view(R, C)
+    p = ((qm / qm.sum())[:, None] * rows / rows.sum(dim=1, keepdim=True)).reshape(-1)
+    curves = {"inverse": {}, "alias": {}}
+    rates = {}
+    for k in range(14, 27):
+        N = 1 << k
+        u2 = torch.from_numpy(wl.hammersley_u64(N)).to(dev)
+        for name in ("inverse", "alias"):
+            if name == "inverse":
+                rc, _ = rtf.sample_2d(f, u2, want_xy=False)
+            else:
+                rc = rtf.alias_sample_2d(t, u2)
+            rc = rc.view(-1, 2).to(torch.int64)
+            cnt = torch.bincount(rc[:, 0] * C + rc[:, 1], minlength=R * C).to(torch.float64)
+            curves[name][N] = float(((p - cnt / N) ** 2).sum().item())
+            if k == 26:
+                if name == "inverse":
+                    ms = event_time(lambda: rtf.sample_2d(f, u2, want_xy=False), args.steps)
+                else:
+                    ms = event_time(lambda: rtf.alias_sample_2d(t, u2), args.steps)
+                rates[name] = N / (ms * 1e-3)
+        del u2
+    inv, al = curves["inverse"], curves["alias"]
+    Nmax = 1 << 26
+    # the samples the inverse mapping needs to reach the alias mapping's error
+    # at 2^26 (log-log interpolation between measured points), as Fig.
+    # convergence reads its "3x as many samples"
+    target = al[Nmax]
+    Ns = sorted(inv)
+    need = None
+    for a_, b_ in zip(Ns, Ns[1:]):
+        if inv[a_] >= target >= inv[b_]:
+            fr = (np.log(inv[a_]) - np.log(target)) / (np.log(inv[a_]) - np.log(inv[b_]))
+            need = float(np.exp(np.log(a_) + fr * (np.log(b_) - np.log(a_))))
+    res = common("quadratic error e of Hammersley points mapped by the inverse vs the Alias "
+                 "Method", "e ratio alias/inverse at N=2^26", al[Nmax] / inv[Nmax], 0.0, args,
+                 "u64", "C3 map (4096x4096, marginal + rows, quantised): 2D Hammersley sets of "
+                 "N = 2^14..2^26 points through the forest (inverse) and through alias tables",
+                 curve_inverse={str(k_): v_ for k_, v_ in inv.items()},
+                 curve_alias={str(k_): v_ for k_, v_ in al.items()},
+                 inverse_samples_for_alias_error_at_2e26=need,
+                 samples_ratio=(Nmax / need) if need else None,
+                 pairs_s_at_2e26=rates)
+    res["higher_is_better"] = False
     print(json.dumps(res), flush=True)
 
 

@@ -316,6 +316,70 @@ rtf_status rtf_backward_static(const rtf_forest *f, const int64_t *sample_off,
                                const double *scale, double *grad_w,
                                hipStream_t stream);
 
+/* ---- the Alias Method: the non-monotone comparison mapping (Sec. 2.6) ---- */
+
+/*
+ * Walker's alias table (Sec. 2.6, Fig. alias_map), the mapping the paper's
+ * quality study compares the inverse against (Figs. results_sine64, 2d_zoom,
+ * convergence).  It maps uniforms to the same distribution, but not
+ * monotonically, so it does not preserve the uniformity of a low-discrepancy
+ * sequence.  Exact integers: item i of a distribution of n weights carries
+ * the mass w_i n, each of the n cells holds W = sum w.  Record j is
+ * { uint64 thr_j; int32 alias_j; int32 unused; }: item j keeps the part thr_j
+ * of cell j, alias_j the rest.  Built by Vose's two-worklist method in a
+ * fixed order (small items, of mass below W, and large ones on two stacks in
+ * increasing index order; each step pairs the top of both and pushes the
+ * large item back by its remaining mass), serial per distribution as the
+ * paper notes known setups are.
+ */
+typedef struct rtf_alias_table {
+    int32_t D;
+    int64_t n_total;
+    void *recs;         /* device: n_total 16-byte records */
+    uint64_t *W;        /* device: D totals */
+    int64_t *elem_off;  /* device: D+1 offsets (copied at build) */
+    uint32_t *status;   /* device: status word */
+} rtf_alias_table;
+
+/* Bytes of workspace for rtf_alias_build; 0 if out of range. */
+size_t rtf_alias_workspace_bytes(int32_t D, int64_t n_total);
+
+/*
+ * Build the alias tables of D distributions stored back to back.
+ *   w         uint32[n_total] weights; elem_off int64[D+1] device offsets as
+ *             in rtf_build_batched (NULL with D == 1)
+ *   ws        rtf_alias_workspace_bytes(D, n_total) bytes, 256-byte aligned;
+ *             it holds the tables afterwards
+ * One thread per distribution runs the serial setup.  A distribution with
+ * W = 0 is reported by rtf_alias_export as RTF_ERR_ZERO_TOTAL and samples
+ * to -1.
+ */
+rtf_status rtf_alias_build(const uint32_t *w, const int64_t *elem_off, int32_t D,
+                           int64_t n_total, void *ws, size_t ws_bytes,
+                           hipStream_t stream, rtf_alias_table *out);
+
+/*
+ * Sample: xi = u 2^-64 lies in cell j = floor(u n / 2^64) at the offset
+ * r = u n mod 2^64; the item is j if floor(r W / 2^64) < thr_j, else
+ * alias_j (an exact test).  sample_off int64[D+1] as in rtf_sample_batched
+ * (NULL with D == 1); indices are local to each distribution.
+ */
+rtf_status rtf_alias_sample(const rtf_alias_table *t, const int64_t *sample_off,
+                            const uint64_t *u, int64_t S, int32_t *out_idx,
+                            hipStream_t stream);
+
+/* Pairs as rtf_sample_2d: table 0 is the marginal over R = D - 1 rows,
+ * table r + 1 is row r; u2[2s] picks the row, u2[2s+1] the column.  u2 must
+ * be 16-byte and out_rc 8-byte aligned. */
+rtf_status rtf_alias_sample_2d(const rtf_alias_table *t, const uint64_t *u2, int64_t S,
+                               int32_t *out_rc, hipStream_t stream);
+
+/* Synchronise and copy the tables to host buffers (each may be NULL):
+ * h_thr uint64[n_total], h_alias int32[n_total] (local indices), h_W
+ * uint64[D]; returns the first error the build recorded. */
+rtf_status rtf_alias_export(const rtf_alias_table *t, uint64_t *h_thr, int32_t *h_alias,
+                            uint64_t *h_W, hipStream_t stream);
+
 /* ---- inspection --------------------------------------------------------- */
 
 /* Synchronise the stream and return the first error recorded in the forest's

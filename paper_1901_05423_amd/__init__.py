@@ -56,11 +56,23 @@ class rtf_forest(ctypes.Structure):
     ]
 
 
+class rtf_alias_table(ctypes.Structure):
+    _fields_ = [
+        ("D", ctypes.c_int32),
+        ("n_total", ctypes.c_int64),
+        ("recs", ctypes.c_void_p),
+        ("W", ctypes.c_void_p),
+        ("elem_off", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
 _P, _I32, _I64, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 _FP = ctypes.POINTER(rtf_forest)
+_AP = ctypes.POINTER(rtf_alias_table)
 SIGNATURES = {
     "rtf_workspace_bytes": (_SZ, [_I64, _I64]),
     "rtf_workspace_bytes_batched": (_SZ, [_I32, _I64, _I64]),
@@ -83,6 +95,11 @@ SIGNATURES = {
     "rtf_forest_depth": (ctypes.c_int, [_FP, _P, _P]),
     "rtf_forest_export": (ctypes.c_int, [_FP, _P, _P, _P, _P]),
     "rtf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "rtf_alias_workspace_bytes": (_SZ, [_I32, _I64]),
+    "rtf_alias_build": (ctypes.c_int, [_P, _P, _I32, _I64, _P, _SZ, _P, _AP]),
+    "rtf_alias_sample": (ctypes.c_int, [_AP, _P, _P, _I64, _P, _P]),
+    "rtf_alias_sample_2d": (ctypes.c_int, [_AP, _P, _I64, _P, _P]),
+    "rtf_alias_export": (ctypes.c_int, [_AP, _P, _P, _P, _P]),
 }
 
 
@@ -394,6 +411,66 @@ def backward_static(f: Forest, u, idx, grad_x, scale, sample_off=None, out=None,
                                      _ptr(grad_x), u.numel(), _ptr(scale), _ptr(grad_w),
                                      _stream(stream)), "rtf_backward_static")
     return grad_w
+
+
+class AliasTable:
+    """Alias tables built by rtf_alias_build (the non-monotone comparison
+    mapping of Sec. 2.6); owns its workspace."""
+
+    def __init__(self, ws, desc, device):
+        self.ws, self.desc, self.device = ws, desc, device
+
+    def export(self, stream=None):
+        """Host copies (thr uint64[n_total], alias int32[n_total], W uint64[D]);
+        raises on an error the build recorded."""
+        import numpy as np
+        n, D = self.desc.n_total, self.desc.D
+        thr = np.zeros(n, np.uint64)
+        alias = np.zeros(n, np.int32)
+        W = np.zeros(D, np.uint64)
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(lib().rtf_alias_export(ctypes.byref(self.desc), p(thr), p(alias), p(W),
+                                      _stream(stream)), "rtf_alias_export")
+        return thr, alias, W
+
+
+def alias_build(w, elem_off=None, stream=None) -> AliasTable:
+    """Alias tables of D distributions of uint32 weights (rtf_alias_build)."""
+    torch = _torch()
+    _dev(w, torch.uint32, "w")
+    D = 1 if elem_off is None else elem_off.numel() - 1
+    if elem_off is not None:
+        _dev(elem_off, torch.int64, "elem_off")
+    nb = lib().rtf_alias_workspace_bytes(D, w.numel())
+    if nb == 0:
+        raise RtfError(RTF_ERR_SIZE, "rtf_alias_workspace_bytes")
+    ws = _workspace(nb, w.device)
+    desc = rtf_alias_table()
+    _check(lib().rtf_alias_build(_ptr(w), _ptr(elem_off), D, w.numel(), _ptr(ws), nb,
+                                 _stream(stream), ctypes.byref(desc)), "rtf_alias_build")
+    return AliasTable(ws, desc, w.device)
+
+
+def alias_sample(t: AliasTable, u, sample_off=None, out=None, stream=None):
+    """Indices of the alias mapping (rtf_alias_sample)."""
+    torch = _torch()
+    u = _u(u)
+    idx = out if out is not None else torch.empty(u.numel(), dtype=torch.int32, device=u.device)
+    _check(lib().rtf_alias_sample(ctypes.byref(t.desc), _ptr(sample_off), _ptr(u), u.numel(),
+                                  _ptr(idx), _stream(stream)), "rtf_alias_sample")
+    return idx
+
+
+def alias_sample_2d(t: AliasTable, u2, out=None, stream=None):
+    """(row, column) pairs of the alias mapping (rtf_alias_sample_2d);
+    u2 uint64[S, 2]."""
+    torch = _torch()
+    u2 = _u(u2)
+    S = u2.numel() // 2
+    rc = out if out is not None else torch.empty((S, 2), dtype=torch.int32, device=u2.device)
+    _check(lib().rtf_alias_sample_2d(ctypes.byref(t.desc), _ptr(u2), S, _ptr(rc),
+                                     _stream(stream)), "rtf_alias_sample_2d")
+    return rc
 
 
 def cells_like(elem_off, ratio: float = 1.0):

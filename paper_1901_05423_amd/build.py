@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtforest.so")
 SOURCES = ["rtf_abi.hip", "rtf_build.hip", "rtf_sample.hip", "rtf_quantize.hip",
-           "rtf_backward.hip", "rtf_noalloc.hip"]
+           "rtf_backward.hip", "rtf_noalloc.hip", "rtf_alias.hip"]
 # measurement aid: the sampling kernels' memory pattern without the search
 PROBE_LIB = os.path.join(HERE, "librtf_probe.so")
 PROBE_SOURCES = ["rtf_probe.hip"]

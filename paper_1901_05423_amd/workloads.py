@@ -112,3 +112,28 @@ def table1_weights(family: str, n: int) -> np.ndarray:
     else:
         raise ValueError(family)
     return w.astype(np.float32)
+
+
+def hammersley_u64(N: int) -> np.ndarray:
+    """The two-dimensional Hammersley point set of N = 2^k points (k >= 1) as
+    0.64 fixed-point pairs, shape [N, 2]: (i / N, the base-2 radical inverse
+    of i), i = 0 .. N-1 -- the low-discrepancy input of the paper's quality
+    study (Figs. 2d_zoom, convergence).  Both components are exact: i / N is
+    i << (64 - k), and the radical inverse mirrors the k bits of i about the
+    binary point."""
+    N = int(N)
+    k = N.bit_length() - 1
+    if N < 2 or N != 1 << k or k > 32:
+        raise ValueError("N must be a power of two in [2, 2^32]")
+    i = np.arange(N, dtype=np.uint64)
+    r = i.astype(np.uint32)
+    # reverse the 32 bits of i (swap halves, bytes, nibbles, pairs, bits)
+    r = (r >> np.uint32(16)) | (r << np.uint32(16))
+    r = ((r >> np.uint32(8)) & np.uint32(0x00FF00FF)) | ((r & np.uint32(0x00FF00FF)) << np.uint32(8))
+    r = ((r >> np.uint32(4)) & np.uint32(0x0F0F0F0F)) | ((r & np.uint32(0x0F0F0F0F)) << np.uint32(4))
+    r = ((r >> np.uint32(2)) & np.uint32(0x33333333)) | ((r & np.uint32(0x33333333)) << np.uint32(2))
+    r = ((r >> np.uint32(1)) & np.uint32(0x55555555)) | ((r & np.uint32(0x55555555)) << np.uint32(1))
+    out = np.empty((N, 2), np.uint64)
+    out[:, 0] = i << np.uint64(64 - k)
+    out[:, 1] = r.astype(np.uint64) << np.uint64(32)
+    return out
