@@ -601,6 +601,11 @@ def run_table1(args):
         t_sw = event_time(lambda: rtf.sample(f, u, out=(idx, x)), args.steps)
         assert torch.equal(idx, ref_idx), "collapsed and binary descents differ"
         wide = f.wide_view().cpu().numpy()
+        # the depth fallback (Sec. 3): degenerate cell trees rebuilt balanced
+        rebuilt = f.balance()
+        t_sb = event_time(lambda: rtf.sample(f, u, out=(idx, x)), args.steps)
+        assert torch.equal(idx, ref_idx), "balanced and radix descents differ"
+        keyb, childb, tableb, _, (Kb, auxb) = f.export(with_cells=True)
         out[fam] = {
             "loads_cutpoint_bisection": load_stats(loads_cutpoint(key, table, m, sub)),
             "loads_forest_alg2": load_stats(loads_forest_alg2(key, child, table, m, sub)),
@@ -608,7 +613,13 @@ def run_table1(args):
                                                                     sub)),
             "loads_forest_records_collapsed": load_stats(
                 loads_forest_records(key, child, table, K, aux, m, sub, wide=wide)),
+            "loads_forest_alg2_balanced": load_stats(loads_forest_alg2(keyb, childb, tableb, m,
+                                                                       sub)),
+            "loads_forest_records_balanced": load_stats(
+                loads_forest_records(keyb, childb, tableb, Kb, auxb, m, sub)),
+            "cells_rebuilt_by_fallback": rebuilt,
             "samples_s": {"forest": S / (t_s * 1e-3), "forest_collapsed": S / (t_sw * 1e-3),
+                          "forest_balanced": S / (t_sb * 1e-3),
                           "cutpoint_bisection": S / (t_cb * 1e-3),
                           "binary_search": S / (t_bs * 1e-3)},
             "build_ms": t_b,

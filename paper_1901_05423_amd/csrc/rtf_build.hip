@@ -496,21 +496,28 @@ constexpr int LEAF_N = TILE + 2 * HALO;
 constexpr int LVL_N = LEAF_N - 1;  // real boundaries; lvl[LVL_N] is padding
 static_assert(LEAF_N % 8 == 0, "levels are read 8 at a time");
 static_assert(2 * HALO == 64, "wave 0 loads both halos, one leaf per lane");
-static_assert(WIN % 4 == 0 && (LEAF_N * 12) % 16 == 0, "16-byte clears of slot and window");
-constexpr int32_t SLOT_EMPTY = INT32_MIN;  // never a node or leaf reference
+// Child slots hold local node indices (16 bits) and window entries 16-bit
+// owner codes, so that the tile's LDS (about 38 KB) lets four blocks share a
+// CU.
+static_assert(WIN % 8 == 0 && (2 * TILE) % 8 == 0, "16-byte clears of slot and window");
+// An empty child slot holds -1 in LDS and reads as SLOT_EMPTY, never a node
+// or leaf reference.
+constexpr int32_t SLOT_EMPTY = INT32_MIN;
 
 // Owner codes of the guide cells staged in the window: which local leaf a
-// cell record comes from and how.
-constexpr int32_t WIN_EMPTY = -1;
-constexpr int32_t WIN_ROOT = 0 << 16;  // the cell's first node
-constexpr int32_t WIN_HEAD = 1 << 16;  // covered by the leaf before that node
-constexpr int32_t WIN_TAIL = 2 << 16;  // covered by a distribution's last leaf
+// cell record comes from (low 14 bits) and how (top 2 bits).
+constexpr uint16_t WIN_EMPTY = 0xFFFF;
+constexpr uint16_t WIN_ROOT = 0 << 14;  // the cell's first node
+constexpr uint16_t WIN_HEAD = 1 << 14;  // covered by the leaf before that node
+constexpr uint16_t WIN_TAIL = 2 << 14;  // covered by a distribution's last leaf
+constexpr uint16_t WIN_KIND = 0xC000, WIN_LEAF = 0x3FFF;
+static_assert(LEAF_N <= WIN_LEAF, "local leaf indices fit an owner code");
 
 struct alignas(16) TileSmem {
     uint64_t key[LEAF_N];
     int32_t cell[LEAF_N];
-    int32_t slot[2 * TILE];  // child slots of the tile's own nodes
-    int32_t win[WIN];        // owner codes of cells c_begin .. c_begin + WIN - 1
+    int16_t slot[2 * TILE];  // child slots of the tile's own nodes (local node index)
+    uint16_t win[WIN];       // owner codes of cells c_begin .. c_begin + WIN - 1
     uint64_t lvl8[LEAF_N / 8];
     uint64_t wave[BT / 64];
     int64_t c_begin;
@@ -570,24 +577,31 @@ __device__ inline int nearest_ge_right(const TileSmem &sm, int bi, int t) {
     return r < LVL_N ? r : -1;
 }
 
-// write ref into child slot `side` of local node pn if the tile owns it
-__device__ inline void link(TileSmem &sm, int pn, int side, int32_t ref) {
+// write local node `child` into child slot `side` of local node pn if the
+// tile owns it
+__device__ inline void link(TileSmem &sm, int pn, int side, int child) {
     const int s = pn - HALO;
-    if (s >= 0 && s < TILE) sm.slot[2 * s + side] = ref;
+    if (s >= 0 && s < TILE) sm.slot[2 * s + side] = (int16_t)child;
+}
+
+// child slot k as a global reference (SLOT_EMPTY when nothing was linked)
+__device__ inline int32_t slot_ref(const TileSmem &sm, int k, int32_t lb0) {
+    const int16_t v = sm.slot[k];
+    return v < 0 ? SLOT_EMPTY : lb0 + v;
 }
 
 // stage the record of cell c (owner code w) in the window, or store it
 // directly when the cell lies past the window
 // (returns the window position written, or -1)
-__device__ inline int put_cell(TileSmem &sm, Cell *cells, int64_t c, int32_t w, int32_t lb0) {
+__device__ inline int put_cell(TileSmem &sm, Cell *cells, int64_t c, uint16_t w, int32_t lb0) {
     const int64_t x = c - sm.c_begin;
     if (x >= 0 && x < WIN) {
         sm.win[x] = w;
         return (int)x;
     }
-    const int li = w & 0xffff;
+    const int li = w & WIN_LEAF;
     const int32_t g = lb0 + li;
-    if ((w & ~0xffff) == WIN_HEAD) store_covered(cells, c, sm.key[li - 1], sm.key[li], g - 1);
+    if ((w & WIN_KIND) == WIN_HEAD) store_covered(cells, c, sm.key[li - 1], sm.key[li], g - 1);
     else store_covered(cells, c, sm.key[li], KEY_END, g);  // WIN_TAIL
     return -1;
 }
@@ -603,7 +617,7 @@ __device__ inline void root_cell_record(const TileSmem &sm, Cell *cells, int64_t
     }
     // child 1 of a cell's first node: the cell tree's root (read only when
     // the cell holds more than CELL_BOUNDS leaves, so it is an internal node)
-    root_record(cells, c, lb0 + li, sm.key[li - 1], key, cell, sm.slot[2 * (li - HALO) + 1]);
+    root_record(cells, c, lb0 + li, sm.key[li - 1], key, cell, slot_ref(sm, 2 * (li - HALO) + 1, lb0));
 }
 
 // Phase 1 of k_build_tile (thread t owns ITEMS consecutive leaves): prefix
@@ -691,10 +705,12 @@ __device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
     }
 }
 
-// Three blocks per CU (the LDS allows three): the batched instance is held
-// to 80 registers for that, at the price of a few spilled ones.
+// The LDS allows four blocks per CU.  The single-distribution instance fits
+// 64 registers and runs four (eight waves per SIMD); the batched instance,
+// which needs more, is held to 80 registers for three blocks, at the price
+// of a few spilled ones.
 template <bool BATCHED>
-__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_build_tile(BuildArgs a, bool vec) {
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(BATCHED ? 6 : 8))) void k_build_tile(BuildArgs a, bool vec) {
     __shared__ TileSmem sm;
     const int tid = threadIdx.x;
     const int64_t t = blockIdx.x;
@@ -731,10 +747,10 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_
         }
     }
     {
-        const int4 se = make_int4(SLOT_EMPTY, SLOT_EMPTY, SLOT_EMPTY, SLOT_EMPTY);
-        const int4 we = make_int4(WIN_EMPTY, WIN_EMPTY, WIN_EMPTY, WIN_EMPTY);
-        for (int x = tid; x < 2 * TILE / 4; x += BT) reinterpret_cast<int4 *>(sm.slot)[x] = se;
-        for (int x = tid; x < WIN / 4; x += BT) reinterpret_cast<int4 *>(sm.win)[x] = we;
+        // 16-bit entries, eight per 16-byte store; both empty codes are all ones
+        const int4 ones = make_int4(-1, -1, -1, -1);
+        for (int x = tid; x < 2 * TILE / 8; x += BT) reinterpret_cast<int4 *>(sm.slot)[x] = ones;
+        for (int x = tid; x < WIN / 8; x += BT) reinterpret_cast<int4 *>(sm.win)[x] = ones;
     }
     if (tid == 0) {
         // first guide cell whose record comes from a leaf of this tile
@@ -809,9 +825,8 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_
                 }
                 if (R >= LVL_N) R = -1;  // the padding byte: beyond the window
                 if (active && L >= 0 && R >= 0) {  // else the fix-up finds the parent
-                    const int32_t ref = lb0 + bi + 1;
-                    if (lL > lR) link(sm, R + 1, 0, ref);
-                    else link(sm, L + 1, 1, ref);
+                    if (lL > lR) link(sm, R + 1, 0, bi + 1);
+                    else link(sm, L + 1, 1, bi + 1);
                 }
             }
         }
@@ -833,8 +848,8 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_
             // the slot in phase 3
             const int l2 = lvl_at(sm, li - 2), l1 = lvl_at(sm, li - 1), l0 = lvl_at(sm, li);
             const bool root = l1 == SENT;
-            c0 = root ? ((kj == 0) ? ~gj : ~(gj - 1)) : (l2 > l1 ? ~(gj - 1) : sm.slot[2 * jl]);
-            c1 = l1 <= l0 ? ~gj : sm.slot[2 * jl + 1];
+            c0 = root ? ((kj == 0) ? ~gj : ~(gj - 1)) : (l2 > l1 ? ~(gj - 1) : slot_ref(sm, 2 * jl, lb0));
+            c1 = l1 <= l0 ? ~gj : slot_ref(sm, 2 * jl + 1, lb0);
             if (c0 == SLOT_EMPTY || c1 == SLOT_EMPTY) push_item(sm, gj);
             // leaf gj+1 carries mass and belongs to gj's distribution
             const int32_t nc = sm.cell[li + 1];
@@ -842,7 +857,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_
             if (root) {
                 const int64_t x = cj - sm.c_begin;
                 if (x >= 0 && x < WIN) {
-                    sm.win[x] = WIN_ROOT | li;
+                    sm.win[x] = (uint16_t)(WIN_ROOT | li);
                     xmax = max(xmax, (int)x);
                 } else {
                     root_cell_record(sm, a.cells, cj, li, lb0);
@@ -852,7 +867,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_
                     if (cj - pc - 1 > RUN_CAP) push_run(a, pc + 1, cj, gj - 1, sm.key[li - 1], kj);
                     else
                         for (int64_t c = pc + 1; c < cj; ++c)
-                            xmax = max(xmax, put_cell(sm, a.cells, c, WIN_HEAD | li, lb0));
+                            xmax = max(xmax, put_cell(sm, a.cells, c, (uint16_t)(WIN_HEAD | li), lb0));
                 }
             }
             // the distribution's last leaf with mass covers the remaining cells
@@ -863,7 +878,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_
                     if (cend - cj - 1 > RUN_CAP) push_run(a, cj + 1, cend, gj, kj, KEY_END);
                     else
                         for (int64_t c = cj + 1; c < cend; ++c)
-                            xmax = max(xmax, put_cell(sm, a.cells, c, WIN_TAIL | li, lb0));
+                            xmax = max(xmax, put_cell(sm, a.cells, c, (uint16_t)(WIN_TAIL | li), lb0));
                 }
             }
         }
@@ -878,12 +893,12 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(6))) void k_
     // ---- phase 5: the staged guide cells, 64 consecutive records per wave ---
     const int span = sm.win_hi + 1;
     for (int x = tid; x < span; x += BT) {
-        const int32_t w = sm.win[x];
+        const uint16_t w = sm.win[x];
         if (w == WIN_EMPTY) continue;
         const int64_t c = sm.c_begin + x;
-        const int li = w & 0xffff;
+        const int li = w & WIN_LEAF;
         const int32_t g = lb0 + li;
-        const int32_t kind = w & ~0xffff;
+        const int kind = w & WIN_KIND;
         if (kind == WIN_ROOT) root_cell_record(sm, a.cells, c, li, lb0);
         else if (kind == WIN_HEAD) store_covered(a.cells, c, sm.key[li - 1], sm.key[li], g - 1);
         else store_covered(a.cells, c, sm.key[li], KEY_END, g);
