@@ -81,6 +81,8 @@ def parse():
     p.add_argument("--cell-ratio", type=float, default=None,
                    help="guide cells per weight m/n; default: the autotuner's choice for "
                         "this shape (tune.best_cell_ratio, timed on the same data)")
+    p.add_argument("--collapsed", action="store_true",
+                   help="with --cell-ratio on a batched workload: descend collapsed 4-ary records")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--profile", action="store_true",
                    help="few steps, no baselines (for rocprofv3 runs)")
@@ -638,7 +640,7 @@ def batch_choice(args, v, u, eo, so):
     --cell-ratio fixes the ratio (binary descent), else the autotuner times
     quantise + build (+ collapse) + sample over its candidates on this data."""
     if args.cell_ratio is not None:
-        return args.cell_ratio, False, {"source": "fixed"}
+        return args.cell_ratio, bool(args.collapsed), {"source": "fixed"}
     from paper_1901_05423_amd import tune
     r, c, times = tune.best_batched(v, u, eo, so, use_cache=False)
     return r, c, {"source": "tuner", "ms_by_ratio_and_collapsed": times}
@@ -773,7 +775,7 @@ def run_c3(args):
         rtf.sample_2d(f, u2, out=(rc, xy))
 
     if args.cell_ratio is not None:
-        candidates, source = [(args.cell_ratio, False)], "fixed"
+        candidates, source = [(args.cell_ratio, bool(args.collapsed))], "fixed"
     else:
         candidates, source = [(0.125, False), (0.25, False), (0.5, False), (0.25, True),
                               (0.5, True), (1.0, True)], "tuner"
