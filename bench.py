@@ -220,11 +220,17 @@ def load_stats(loads):
 def timed(fn, start, stop, reps, before=None):
     """Median and all times (ms) of fn() over reps runs, each bracketed by HIP
     events on the current stream (the stream the library launches on);
-    before(), if given, runs ahead of each bracket (e.g. a cache flush)."""
+    before(), if given, runs ahead of each bracket (e.g. a cache flush).
+    A short GPU spin (about 40 us) runs ahead of each bracket, so that the host
+    has enqueued all of fn's kernels when the start event fires: the bracket
+    then holds the kernels back to back, as in the timed steps, and not the
+    host's launch latency."""
+    import torch
     ts = []
     for _ in range(reps):
         if before is not None:
             before()
+        torch.cuda._sleep(100000)
         start.record()
         fn()
         stop.record()
