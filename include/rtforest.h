@@ -394,6 +394,29 @@ rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, void *h_cells,
                              uint64_t *h_W, hipStream_t stream);
 
 /*
+ * The inverse of rtf_forest_export, for tests: a forest built elsewhere (for
+ * instance by a CPU reference) is copied into a workspace so that the
+ * sampling and backward calls can run on it.
+ *   h_nodes     host: n_total 16-byte node records, as rtf_forest_export gives
+ *   h_cells     host: m_total 64-byte guide cell records, as rtf_forest_export
+ *               gives (keys and aux must follow the record layout above)
+ *   h_W         host: uint64[D] totals
+ *   h_elem_off, h_cell_off  host: int64[D+1] offsets as in rtf_build_batched
+ *               (NULL with D == 1)
+ *   ws          rtf_workspace_bytes_batched(D, n_total, m_total) bytes,
+ *               256-byte aligned (rtf_workspace_bytes(n, m) with D == 1)
+ * The per-distribution parameters are derived from the totals as the build
+ * derives them.  Offsets that are not strictly increasing from 0 to n_total
+ * (m_total) give RTF_ERR_INVALID_ARG.  Synchronises the stream.  The records
+ * are not checked: a forest that breaks the layout samples undefined values
+ * (but a reference outside the forest yields index -1, not a fault).
+ */
+rtf_status rtf_forest_import(const void *h_nodes, const void *h_cells, const uint64_t *h_W,
+                             const int64_t *h_elem_off, const int64_t *h_cell_off, int32_t D,
+                             int64_t n_total, int64_t m_total, void *ws, size_t ws_bytes,
+                             hipStream_t stream, rtf_forest *out);
+
+/*
  * The deepest search of the forest, counted as Alg. 2 counts memory reads:
  * the guide entry plus the nodes visited down to the leaf, maximised over
  * every uniform (over the leaves with positive weight, each from the cell

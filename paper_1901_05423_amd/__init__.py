@@ -94,6 +94,7 @@ SIGNATURES = {
     "rtf_check": (ctypes.c_int, [_FP, _P]),
     "rtf_forest_depth": (ctypes.c_int, [_FP, _P, _P]),
     "rtf_forest_export": (ctypes.c_int, [_FP, _P, _P, _P, _P]),
+    "rtf_forest_import": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I64, _I64, _P, _SZ, _P, _FP]),
     "rtf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rtf_alias_workspace_bytes": (_SZ, [_I32, _I64]),
     "rtf_alias_build": (ctypes.c_int, [_P, _P, _I32, _I64, _P, _SZ, _P, _AP]),
@@ -235,6 +236,19 @@ class Forest:
         off = self.desc.cells - self.ws.data_ptr()
         return self.ws[off:off + CELL_BYTES * self.m_total].view(torch.int64).view(
             self.m_total, CELL_KEYS + 1)
+
+    def export_raw(self, stream=None):
+        """Host copies of the records as stored: node records uint64 [n, 2],
+        cell records uint64 [m, 8], totals uint64 [D] (what rtf_forest_import
+        takes back)."""
+        import numpy as np
+        raw = np.zeros((self.n_total, 2), np.uint64)
+        cells = np.zeros((self.m_total, CELL_KEYS + 1), np.uint64)
+        W = np.zeros(self.D, np.uint64)
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(lib().rtf_forest_export(ctypes.byref(self.desc), p(raw), p(cells), p(W),
+                                       _stream(stream)), "rtf_forest_export")
+        return raw, cells, W
 
     def export(self, stream=None, with_cells=False):
         """Host copies: key uint64[n], child int32[n, 2], table int32[m] (the guide
@@ -471,6 +485,31 @@ def alias_sample_2d(t: AliasTable, u2, out=None, stream=None):
     _check(lib().rtf_alias_sample_2d(ctypes.byref(t.desc), _ptr(u2), S, _ptr(rc),
                                      _stream(stream)), "rtf_alias_sample_2d")
     return rc
+
+
+def forest_import(nodes_raw, cells_raw, W, elem_off=None, cell_off=None, device="cuda:0",
+                  stream=None) -> Forest:
+    """rtf_forest_import: a forest from host records (uint64 [n, 2] node
+    records and uint64 [m, 8] cell records as Forest.export_raw gives them,
+    uint64 [D] totals, int64 [D+1] host offsets or None for one distribution)."""
+    import numpy as np
+    torch = _torch()
+    nodes_raw = np.ascontiguousarray(nodes_raw, np.uint64)
+    cells_raw = np.ascontiguousarray(cells_raw, np.uint64)
+    W = np.ascontiguousarray(W, np.uint64)
+    n, m, D = nodes_raw.shape[0], cells_raw.shape[0], W.size
+    L = lib()
+    nb = L.rtf_workspace_bytes_batched(D, n, m)
+    if nb == 0:
+        raise RtfError(RTF_ERR_SIZE, "rtf_workspace_bytes_batched")
+    ws = _workspace(nb, torch.device(device))
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None  # noqa: E731
+    eo = np.ascontiguousarray(elem_off, np.int64) if elem_off is not None else None
+    co = np.ascontiguousarray(cell_off, np.int64) if cell_off is not None else None
+    desc = rtf_forest()
+    _check(L.rtf_forest_import(p(nodes_raw), p(cells_raw), p(W), p(eo), p(co), D, n, m, _ptr(ws), nb,
+                               _stream(stream), ctypes.byref(desc)), "rtf_forest_import")
+    return Forest(ws, desc, torch.device(device))
 
 
 def cells_like(elem_off, ratio: float = 1.0):

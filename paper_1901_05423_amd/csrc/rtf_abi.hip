@@ -356,6 +356,94 @@ rtf_status rtf_forest_export(const rtf_forest *f, void *h_nodes, void *h_cells, 
     return RTF_OK;
 }
 
+rtf_status rtf_forest_import(const void *h_nodes, const void *h_cells, const uint64_t *h_W,
+                             const int64_t *h_elem_off, const int64_t *h_cell_off, int32_t D,
+                             int64_t n_total, int64_t m_total, void *ws, size_t ws_bytes,
+                             hipStream_t stream, rtf_forest *out) {
+    if (!h_nodes || !h_cells || !h_W || !ws || !out || !aligned(ws, 256)) return RTF_ERR_INVALID_ARG;
+    if (D > 1 && (!h_elem_off || !h_cell_off)) return RTF_ERR_INVALID_ARG;
+    if (n_total < 1 || m_total < 1 || D < 1) return RTF_ERR_INVALID_ARG;
+    if (!sizes_ok(D, n_total, m_total)) return RTF_ERR_SIZE;
+    const Layout L = make_layout(D, n_total, m_total);
+    if (ws_bytes < L.total) return RTF_ERR_WORKSPACE;
+    // offsets and per-distribution parameters, as the build's scan kernel
+    // derives them from the totals
+    int64_t *eo = static_cast<int64_t *>(malloc(sizeof(int64_t) * (size_t)(D + 1)));
+    int64_t *co = static_cast<int64_t *>(malloc(sizeof(int64_t) * (size_t)(D + 1)));
+    Dist *dist = static_cast<Dist *>(malloc(sizeof(Dist) * (size_t)D));
+    uint32_t *status = static_cast<uint32_t *>(calloc(64, sizeof(uint32_t)));  // the 256-byte status block
+    rtf_status rc = RTF_OK;
+    if (!eo || !co || !dist || !status) rc = RTF_ERR_INVALID_ARG;
+    uint64_t G = 0;
+    for (int32_t q = 0; rc == RTF_OK && q <= D; ++q) {
+        eo[q] = D > 1 ? h_elem_off[q] : (q ? n_total : 0);
+        co[q] = D > 1 ? h_cell_off[q] : (q ? m_total : 0);
+        if (q > 0 && (eo[q] <= eo[q - 1] || co[q] <= co[q - 1])) rc = RTF_ERR_INVALID_ARG;
+    }
+    if (rc == RTF_OK && (eo[0] != 0 || co[0] != 0 || eo[D] != n_total || co[D] != m_total))
+        rc = RTF_ERR_INVALID_ARG;
+    for (int32_t d = 0; rc == RTF_OK && d < D; ++d) {
+        Dist P;
+        memset(&P, 0, sizeof P);
+        P.W = h_W[d];
+        P.G0 = G;
+        G += P.W;
+        P.eo = eo[d];
+        P.n = eo[d + 1] - eo[d];
+        P.co = co[d];
+        P.m = co[d + 1] - co[d];
+        if (P.W == 0) {
+            P.flags = DIST_ZERO;
+            status[0] |= status_bit(RTF_ERR_ZERO_TOTAL);
+        } else {
+            P.s = (uint32_t)clz64(P.W);
+            P.v = reciprocal_2by1(P.W << P.s);
+        }
+        if (P.m > 1 && (P.m & (P.m - 1)) == 0)
+            P.flags |= (uint32_t)(64 - __builtin_ctzll((uint64_t)P.m)) << DIST_SHIFT_BIT;
+        dist[d] = P;
+    }
+    char *b = static_cast<char *>(ws);
+    rtf_forest f;
+    memset(&f, 0, sizeof f);
+    f.D = D;
+    f.tile = TILE;
+    f.n_total = n_total;
+    f.m_total = m_total;
+    f.nodes = b + L.nodes;
+    f.cells = b + L.cells;
+    f.dists = b + L.dists;
+    f.elem_off = reinterpret_cast<int64_t *>(b + L.eoff);
+    f.cell_off = reinterpret_cast<int64_t *>(b + L.coff);
+    f.status = reinterpret_cast<uint32_t *>(b + L.status);
+    f.scratch = b + L.tsum;
+    f.scratch_bytes = L.total - L.tsum;
+    if (rc == RTF_OK) {
+        const struct {
+            void *dst;
+            const void *src;
+            size_t bytes;
+        } copies[] = {{f.nodes, h_nodes, sizeof(Node) * (size_t)n_total},
+                      {f.cells, h_cells, sizeof(Cell) * (size_t)m_total},
+                      {f.dists, dist, sizeof(Dist) * (size_t)D},
+                      {f.elem_off, eo, sizeof(int64_t) * (size_t)(D + 1)},
+                      {f.cell_off, co, sizeof(int64_t) * (size_t)(D + 1)},
+                      {f.status, status, 256}};
+        for (const auto &c : copies)
+            if (rc == RTF_OK &&
+                hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+                rc = RTF_ERR_HIP;
+        // the host staging buffers must outlive the copies
+        if (hipStreamSynchronize(stream) != hipSuccess && rc == RTF_OK) rc = RTF_ERR_HIP;
+    }
+    free(eo);
+    free(co);
+    free(dist);
+    free(status);
+    if (rc == RTF_OK) *out = f;
+    return rc;
+}
+
 const char *rtf_status_string(rtf_status s) {
     switch (s) {
     case RTF_OK: return "RTF_OK";

@@ -102,6 +102,20 @@ def test_argument_errors_before_launch(L):
     assert r == rtf.RTF_ERR_SIZE
     assert L.rtf_backward_static(None, None, None, None, None, 0, fake, fake, None) == \
         rtf.RTF_ERR_INVALID_ARG
+    # import: argument and offset checks happen on the host, before any copy
+    f3 = rtf.rtf_forest()
+    W = (ctypes.c_uint64 * 2)(5, 7)
+    r = L.rtf_forest_import(None, fake, W, None, None, 1, 10, 10, fake, 1 << 20, None,
+                            ctypes.byref(f3))
+    assert r == rtf.RTF_ERR_INVALID_ARG
+    bad_eo = (ctypes.c_int64 * 3)(0, 6, 5)  # not increasing
+    co = (ctypes.c_int64 * 3)(0, 5, 10)
+    r = L.rtf_forest_import(fake, fake, W, bad_eo, co, 2, 10, 10, fake, 1 << 30, None,
+                            ctypes.byref(f3))
+    assert r == rtf.RTF_ERR_INVALID_ARG
+    r = L.rtf_forest_import(fake, fake, W, None, None, 1, 1000, 1000, fake, 64, None,
+                            ctypes.byref(f3))
+    assert r == rtf.RTF_ERR_WORKSPACE
     for c in range(7):
         assert L.rtf_status_string(c).decode().startswith("RTF_")
 
