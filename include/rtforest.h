@@ -350,9 +350,11 @@ size_t rtf_alias_workspace_bytes(int32_t D, int64_t n_total);
  *             in rtf_build_batched (NULL with D == 1)
  *   ws        rtf_alias_workspace_bytes(D, n_total) bytes, 256-byte aligned;
  *             it holds the tables afterwards
- * One thread per distribution runs the serial setup.  A distribution with
- * W = 0 is reported by rtf_alias_export as RTF_ERR_ZERO_TOTAL and samples
- * to -1.
+ * One thread per distribution runs the serial setup, so a distribution of n
+ * items costs n dependent steps on one thread: the call suits many small or
+ * medium tables (the rows of a 2D map), not one table of millions of items.
+ * A distribution with W = 0 is reported by rtf_alias_export as
+ * RTF_ERR_ZERO_TOTAL and samples to -1.
  */
 rtf_status rtf_alias_build(const uint32_t *w, const int64_t *elem_off, int32_t D,
                            int64_t n_total, void *ws, size_t ws_bytes,
@@ -370,7 +372,8 @@ rtf_status rtf_alias_sample(const rtf_alias_table *t, const int64_t *sample_off,
 
 /* Pairs as rtf_sample_2d: table 0 is the marginal over R = D - 1 rows,
  * table r + 1 is row r; u2[2s] picks the row, u2[2s+1] the column.  u2 must
- * be 16-byte and out_rc 8-byte aligned. */
+ * be 16-byte and out_rc 8-byte aligned.  A pair whose row has no table (a
+ * marginal with more than D - 1 items) gets (-1, -1). */
 rtf_status rtf_alias_sample_2d(const rtf_alias_table *t, const uint64_t *u2, int64_t S,
                                int32_t *out_rc, hipStream_t stream);
 

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(AT) void k_alias_sample(const AliasRec *__restrict_
 // distribution r + 1; u2[2s] picks the row, u2[2s+1] the column.
 __global__ __launch_bounds__(AT) void k_alias_sample_2d(const AliasRec *__restrict__ recs,
                                                         const int64_t *__restrict__ eoff,
-                                                        const uint64_t *__restrict__ Wd,
+                                                        const uint64_t *__restrict__ Wd, int32_t D,
                                                         const uint64_t *__restrict__ u2, int64_t S,
                                                         int32_t *__restrict__ rc) {
     const int64_t s = (int64_t)blockIdx.x * AT + threadIdx.x;
@@ -130,9 +130,13 @@ __global__ __launch_bounds__(AT) void k_alias_sample_2d(const AliasRec *__restri
     int32_t r = -1, c = -1;
     if (Wm != 0) {
         r = alias_pick(recs, 0, eoff[1], Wm, ua);
-        const int64_t e0 = eoff[r + 1], n = eoff[r + 2] - e0;
-        const uint64_t W = Wd[r + 1];
-        c = W == 0 ? -1 : alias_pick(recs, e0, n, W, ub);
+        if (r + 1 < D) {  // the marginal must have one item per row table 1..D-1
+            const int64_t e0 = eoff[r + 1], n = eoff[r + 2] - e0;
+            const uint64_t W = Wd[r + 1];
+            c = W == 0 ? -1 : alias_pick(recs, e0, n, W, ub);
+        } else {
+            r = -1;
+        }
     }
     *reinterpret_cast<int2 *>(rc + 2 * s) = make_int2(r, c);
 }
@@ -235,7 +239,8 @@ rtf_status rtf_alias_sample_2d(const rtf_alias_table *t, const uint64_t *u2, int
         (reinterpret_cast<uintptr_t>(out_rc) & 7))
         return RTF_ERR_INVALID_ARG;
     hipLaunchKernelGGL(k_alias_sample_2d, dim3((unsigned)((S + AT - 1) / AT)), dim3(AT), 0, stream,
-                       static_cast<const AliasRec *>(t->recs), t->elem_off, t->W, u2, S, out_rc);
+                       static_cast<const AliasRec *>(t->recs), t->elem_off, t->W, t->D, u2, S,
+                       out_rc);
     return hipGetLastError() == hipSuccess ? RTF_OK : RTF_ERR_HIP;
 }
 

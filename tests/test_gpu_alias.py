@@ -65,6 +65,25 @@ def test_alias_zero_total(rtf):
     assert (idx.cpu().numpy()[3:] == -1).all()
 
 
+def test_alias_2d_marginal_longer_than_rows(rtf):
+    """A marginal with more items than there are row tables: a pair whose row
+    has no table gets (-1, -1) instead of reading past the offsets."""
+    note("alias: 2D with a marginal longer than the rows")
+    import torch
+    w = to_dev(np.array([1, 1, 1, 1, 5, 6, 7, 8], np.uint32))  # marginal of 4, two rows of 2
+    eo = to_dev(np.array([0, 4, 6, 8], np.int64))
+    t = rtf.alias_build(w, eo)
+    u2 = to_dev((np.arange(2048, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)))
+    rc = rtf.alias_sample_2d(t, u2).cpu().numpy()
+    torch.cuda.synchronize()
+    # marginal items 2 and 3 (half the mass) have no row table
+    assert ((rc[:, 0] == -1) | (rc[:, 0] < 2)).all()
+    assert ((rc[:, 0] == -1) == (rc[:, 1] == -1)).all()
+    assert 0 < (rc[:, 0] == -1).sum() < rc.shape[0]
+    ok = rc[:, 0] >= 0
+    assert ((rc[ok, 1] >= 0) & (rc[ok, 1] < 2)).all()
+
+
 def small_map(rng, R, C):
     from paper_1901_05423_amd import workloads as wl
     img, marg = wl.map_2d(rng, rows=R, cols=C, spots=2)
