@@ -100,6 +100,14 @@ struct Hit {
 __device__ inline Hit resolve(const Node *nodes, const Wide *wide, const Cell &c, const Dist &P,
                               uint64_t u, int64_t n_total);
 
+// floor(u m / 2^64) for distribution P's m cells, P the same for the whole
+// wave: a shift when m is a power of two (the shift is in the distribution's
+// flags), else the high word of the product
+__device__ inline int64_t cell_in(const Dist &P, uint64_t u) {
+    const uint32_t sh = P.flags >> DIST_SHIFT_BIT;
+    return sh ? (int64_t)(u >> sh) : (int64_t)mulhi64(u, (uint64_t)P.m);
+}
+
 __device__ inline int64_t cell_index(const Dist &P, uint64_t u) {
     return P.co + (int64_t)mulhi64(u, (uint64_t)P.m);
 }
@@ -207,14 +215,17 @@ __device__ inline Hit resolve(const Node *nodes, const Wide *wide, const Cell &c
 
 // x = (i + ((t - C_i) + lo * 2^-64) / w_i) / n with t:lo = u * W, where
 // C_i = floor(U_i * W / 2^64) recovers the exact partial sum from a key.
+// For the sampled i, 0 <= t - C_i < w_i = C_{i+1} - C_i < 2^32 and
+// i - eo < 2^31, so those three convert to FP64 from 32 bits (one
+// instruction each, and the same values).
 __device__ inline double position(const Dist &P, const Hit &h, uint64_t u) {
     const uint64_t W = P.W;
     const uint64_t Ci = mulhi64(h.lo, W);
     const uint64_t Cn = (h.hi == KEY_END) ? W : mulhi64(h.hi, W);
     const uint64_t t = mulhi64(u, W);
     const uint64_t lo = u * W;
-    const double frac = ((double)(t - Ci) + ldexp((double)lo, -64)) / (double)(Cn - Ci);
-    return ((double)(h.i - P.eo) + frac) / (double)P.n;
+    const double frac = ((double)(uint32_t)(t - Ci) + ldexp((double)lo, -64)) / (double)(uint32_t)(Cn - Ci);
+    return ((double)(int32_t)(h.i - P.eo) + frac) / (double)P.n;
 }
 
 // The same, for a leaf found without its keys (the baselines).
@@ -392,8 +403,8 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
                 const int64_t sb = sa + SB_T;
                 const uint64_t ua = __builtin_nontemporal_load(u + sa);
                 const uint64_t ub = __builtin_nontemporal_load(u + (sb < e ? sb : sa));
-                Cell ca = load_cell(sc, (int64_t)mulhi64(ua, (uint64_t)P.m));
-                Cell cb = load_cell(sc, (int64_t)mulhi64(ub, (uint64_t)P.m));
+                Cell ca = load_cell(sc, cell_in(P, ua));
+                Cell cb = load_cell(sc, cell_in(P, ub));
                 pin_cell(ca);
                 pin_cell(cb);
                 const Hit ha = resolve(nodes, wide, ca, P, ua, n_total);
@@ -474,7 +485,7 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
         const Cell *sc = reinterpret_cast<const Cell *>(s_cell);
         for (int64_t s = s_first; s < S; s += T) {
             const u64x2 uu = __builtin_nontemporal_load(up + s);
-            Cell cr = load_cell(sc, (int64_t)mulhi64(uu.x, (uint64_t)M.m));
+            Cell cr = load_cell(sc, cell_in(M, uu.x));
             pin_cell(cr);
             pair(s, uu, cr);
         }
