@@ -24,6 +24,7 @@ C5_DIFF = 5
 H24_UNIFORM = 24
 H24_ZIPF = 25
 TABLE1 = 30  # uniforms for the load-count families
+MAX_SIZE = 40  # the largest single distribution the library accepts
 
 
 def rng(config_id: int) -> np.random.Generator:
