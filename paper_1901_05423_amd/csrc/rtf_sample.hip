@@ -213,19 +213,38 @@ __device__ inline Hit resolve(const Node *nodes, const Wide *wide, const Cell &c
     return h;
 }
 
+// a / b for 0 <= a <= 2^32 and 1 <= b < 2^32 in FP64: the hardware
+// reciprocal refined by two Newton steps, then one correction of the
+// quotient.  Within an ulp or two of the rounded quotient; operands of this
+// range never need the exponent scaling and special cases of a general
+// division.
+__device__ inline double div_small(double a, double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-b, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    const double q = a * r;
+    return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
+
 // x = (i + ((t - C_i) + lo * 2^-64) / w_i) / n with t:lo = u * W, where
 // C_i = floor(U_i * W / 2^64) recovers the exact partial sum from a key.
 // For the sampled i, 0 <= t - C_i < w_i = C_{i+1} - C_i < 2^32 and
 // i - eo < 2^31, so those three convert to FP64 from 32 bits (one
-// instruction each, and the same values).
+// instruction each, and the same values).  The division by n is a product
+// with 1/n, computed once where the distribution is the same for a whole
+// loop; the result is kept at most 1 (it could round one ulp above 1 when
+// the offset in the interval rounds up to w_i in the last leaf).
 __device__ inline double position(const Dist &P, const Hit &h, uint64_t u) {
     const uint64_t W = P.W;
     const uint64_t Ci = mulhi64(h.lo, W);
     const uint64_t Cn = (h.hi == KEY_END) ? W : mulhi64(h.hi, W);
     const uint64_t t = mulhi64(u, W);
     const uint64_t lo = u * W;
-    const double frac = ((double)(uint32_t)(t - Ci) + ldexp((double)lo, -64)) / (double)(uint32_t)(Cn - Ci);
-    return ((double)(int32_t)(h.i - P.eo) + frac) / (double)P.n;
+    const double frac = div_small((double)(uint32_t)(t - Ci) + ldexp((double)lo, -64), (double)(uint32_t)(Cn - Ci));
+    const double x = ((double)(int32_t)(h.i - P.eo) + frac) * (1.0 / (double)P.n);
+    return __builtin_fmin(x, 1.0);
 }
 
 // The same, for a leaf found without its keys (the baselines).
