@@ -130,10 +130,12 @@ __device__ inline void scatter_samples(const Node *__restrict__ nodes, const Dis
             const uint64_t Ci = mulhi64(k0[q], W);
             const uint64_t Cn = k1[q] != ~0ull ? mulhi64(k1[q], W) : W;
             const uint64_t t = mulhi64(us[q], W), lo = us[q] * W;
-            const double wi = (double)(Cn - Ci);
-            const double frac = ((double)(t - Ci) + ldexp((double)lo, -64)) / wi;
+            // w_i < 2^32 for a sampled i (a skipped sample's values are dropped)
+            const double wi = (double)(uint32_t)(Cn - Ci);
+            const double rw = recip_small(__builtin_fmax(wi, 1.0));
+            const double frac = ((double)(uint32_t)(t - Ci) + ldexp((double)lo, -64)) * rw;
             const double xi = ldexp((double)us[q], -64);
-            const double a = g[q] / ((double)P.n * (wi / sq[q]));
+            const double a = g[q] * (sq[q] / (double)P.n) * rw;
             const bool ok = li[q] >= 0;
             if (!UNI && ok && dq[q] != acc_d) {
                 if (acc != 0.0) unsafeAtomicAdd(A + acc_d, acc);
@@ -169,6 +171,7 @@ __device__ inline void scatter_local(const Node *__restrict__ nodes, const Dist 
     __syncthreads();
     if (P.flags & DIST_ZERO) return;  // no sample of it has an index
     const uint32_t w_lo = (uint32_t)P.W;
+    const double sn = sc / (double)n;  // a = g sc / (n w_i): the block's factor
     for (int64_t s0 = c0 + threadIdx.x; s0 < c1; s0 += (int64_t)ILP * SB) {
         int32_t li[ILP];
         uint64_t us[ILP];
@@ -190,9 +193,10 @@ __device__ inline void scatter_local(const Node *__restrict__ nodes, const Dist 
             const uint32_t cn = lc + 1 < n ? s_clo[lc + 1] : w_lo;
             const uint64_t t = mulhi64(us[q], P.W), lo = us[q] * P.W;
             const double wi = (double)(uint32_t)(cn - ci);
-            const double frac = ((double)(uint32_t)((uint32_t)t - ci) + ldexp((double)lo, -64)) / wi;
+            const double rw = recip_small(__builtin_fmax(wi, 1.0));  // w_i >= 1 for a sampled i
+            const double frac = ((double)(uint32_t)((uint32_t)t - ci) + ldexp((double)lo, -64)) * rw;
             const double xi = ldexp((double)us[q], -64);
-            const double a = g[q] / ((double)n * (wi / sc));
+            const double a = g[q] * sn * rw;
             acc += ok ? a * xi : 0.0;
             if (!ok) continue;
             atomicAdd(s_b + lc, a);

@@ -188,6 +188,26 @@ __host__ __device__ inline uint64_t fixed_point_key(uint64_t C, uint64_t d, uint
 // Level of the boundary between two neighbouring leaves: 64 - clz(a ^ b).
 __host__ __device__ inline int level_of(uint64_t a, uint64_t b) { return 64 - clz64(a ^ b); }
 
+// 1 / b in FP64 for 1 <= b < 2^32: the hardware reciprocal refined by two
+// Newton steps, within about an ulp.  Operands of this range never need the
+// exponent scaling and special cases of a general division.
+__device__ inline double recip_small(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-b, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// a / b in FP64 for 0 <= a <= 2^32 and 1 <= b < 2^32: a times the refined
+// reciprocal, then one correction of the quotient; within an ulp or two of
+// the rounded quotient.
+__device__ inline double div_small(double a, double b) {
+    const double r = recip_small(b);
+    const double q = a * r;
+    return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
+
 // The blocks of a launch are dispatched to the 8 XCDs in turn (block b to XCD
 // b mod 8), and each XCD has its own L2.  xcd_block() renumbers the blocks so
 // that each XCD's blocks carry consecutive numbers (a bijection on

@@ -213,21 +213,6 @@ __device__ inline Hit resolve(const Node *nodes, const Wide *wide, const Cell &c
     return h;
 }
 
-// a / b for 0 <= a <= 2^32 and 1 <= b < 2^32 in FP64: the hardware
-// reciprocal refined by two Newton steps, then one correction of the
-// quotient.  Within an ulp or two of the rounded quotient; operands of this
-// range never need the exponent scaling and special cases of a general
-// division.
-__device__ inline double div_small(double a, double b) {
-    double r = __builtin_amdgcn_rcp(b);
-    double e = __builtin_fma(-b, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-b, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    const double q = a * r;
-    return __builtin_fma(__builtin_fma(-b, q, a), r, q);
-}
-
 // x = (i + ((t - C_i) + lo * 2^-64) / w_i) / n with t:lo = u * W, where
 // C_i = floor(U_i * W / 2^64) recovers the exact partial sum from a key.
 // For the sampled i, 0 <= t - C_i < w_i = C_{i+1} - C_i < 2^32 and
