@@ -325,3 +325,40 @@ def test_table1_densities(rtf, orc, family):
     q, _ = orc.quantize(wl.table1_weights(family, n))
     build_and_compare(rtf, orc, q, n, S_extra=40000, seed=11)
     build_and_compare(rtf, orc, q, n // 4, S_extra=40000, seed=12)
+
+
+EXTREMES = np.array([0, 1, 2, 3, 1 << 31, (1 << 32) - 2, (1 << 32) - 1], np.uint64)
+
+
+def adversarial(kind, n, rng):
+    """Weight families that stress ties and degenerate trees: extreme values
+    side by side, blocks of repeated values and zeros, one positive weight."""
+    if kind == "extremes":
+        w = EXTREMES[rng.integers(0, EXTREMES.size, n)]
+    elif kind == "runs":
+        parts, left = [], n
+        while left > 0:
+            ln = int(min(left, rng.integers(1, 3000)))
+            parts.append(np.full(ln, [0, 0, 1, 7, (1 << 32) - 1][rng.integers(0, 5)], np.uint64))
+            left -= ln
+        w = np.concatenate(parts)
+    else:  # one positive weight, at a tile edge or inside a tile
+        w = np.zeros(n, np.uint64)
+        w[int(rng.choice([0, 2047, 2048, n // 2, n - 1]) % n)] = int(rng.integers(1, 1 << 32))
+    if w.sum() == 0:
+        w[0] = 1
+    return w.astype(np.uint32)
+
+
+@pytest.mark.parametrize("kind", ["extremes", "runs", "single"])
+@pytest.mark.parametrize("seed", range(4))
+def test_adversarial_weights(rtf, orc, kind, seed):
+    """Extreme values side by side, long blocks of equal weights and zeros,
+    a single positive weight; sizes spanning several 2048-leaf tiles, guide
+    tables from one cell to 3n."""
+    rng = np.random.default_rng(7000 + 10 * seed + len(kind))
+    n = int(rng.integers(1, 20000))
+    m = max(1, int(n * float(rng.choice([0.001, 0.25, 1.0, 3.0]))))
+    note(f"adversarial {kind} seed={seed} n={n} m={m}")
+    w = adversarial(kind, n, rng)
+    build_and_compare(rtf, orc, w, m, S_extra=5000, seed=seed, baselines=seed == 0)
