@@ -81,6 +81,8 @@ def parse():
     p.add_argument("--cell-ratio", type=float, default=None,
                    help="guide cells per weight m/n; default: the autotuner's choice for "
                         "this shape (tune.best_cell_ratio, timed on the same data)")
+    p.add_argument("--tile", type=int, default=0, choices=[0, 1024, 2048],
+                   help="build tile in elements (0: the tuner's choice on this data)")
     p.add_argument("--collapsed", action="store_true",
                    help="with --cell-ratio on a batched workload: descend collapsed 4-ary records")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -309,10 +311,18 @@ def main():
     holder = {}
 
     ws = torch.empty(rtf.lib().rtf_workspace_bytes(n, m), dtype=torch.uint8, device=dev)
+    tile = args.tile
+    if not tile:
+        # the build tile is the tuner's choice too, at the chosen m
+        from paper_1901_05423_amd import tune
+        rtf.quantize(v, out=(q, scale))
+        tile, tile_times = tune.best_tile(
+            lambda tl: rtf.sample(rtf.build(q, m, ws=ws, tile=tl), u, out=(idx, x)))
+        tune_info["ms_build_plus_sample_by_tile"] = tile_times
 
     def step():
         rtf.quantize(v, out=(q, scale))
-        holder["f"] = rtf.build(q, m, ws=ws)
+        holder["f"] = rtf.build(q, m, ws=ws, tile=tile)
         rtf.sample(holder["f"], u, out=(idx, x))
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
@@ -425,7 +435,8 @@ def main():
                         f"{'uniform(0,1]' if args.kind == 'uniform' else 'Zipf(1.1) permuted'} "
                         f"f32 weights quantised to u32, m={ratio:g}n guide cells ({tune_info['source']}), "
                         f"S=2^{args.log2s} u64 uniforms -> int32 index + f64 position",
-            "n": n, "m": m, "samples": S, "cell_ratio": ratio, "cell_ratio_tuning": tune_info,
+            "n": n, "m": m, "tile": tile, "samples": S, "cell_ratio": ratio,
+            "cell_ratio_tuning": tune_info,
         },
         "phase_ms": {"quantize": t_quant, "build": t_build, "sample": t_sample,
                      "statistic": f"median of {reps}"},
@@ -642,14 +653,16 @@ def run_table1(args):
 
 
 def batch_choice(args, v, u, eo, so):
-    """Guide cells per weight and descent form for a batched workload:
-    --cell-ratio fixes the ratio (binary descent), else the autotuner times
-    quantise + build (+ collapse) + sample over its candidates on this data."""
+    """Guide cells per weight, descent form and build tile for a batched
+    workload: --cell-ratio fixes the ratio (binary descent, --tile or 2048),
+    else the autotuner times quantise + build (+ collapse) + sample over its
+    candidates on this data."""
     if args.cell_ratio is not None:
-        return args.cell_ratio, bool(args.collapsed), {"source": "fixed"}
+        return args.cell_ratio, bool(args.collapsed), args.tile or 2048, {"source": "fixed"}
     from paper_1901_05423_amd import tune
-    r, c, times = tune.best_batched(v, u, eo, so, use_cache=False)
-    return r, c, {"source": "tuner", "ms_by_ratio_and_collapsed": times}
+    tiles = (args.tile,) if args.tile else tune.TILES
+    r, c, tile, times = tune.best_batched(v, u, eo, so, use_cache=False, tiles=tiles)
+    return r, c, tile, {"source": "tuner", "ms_by_ratio_collapsed_tile": times}
 
 
 def run_c4(args):
@@ -667,10 +680,10 @@ def run_c4(args):
     v, u = torch.from_numpy(v_h).to(dev), torch.from_numpy(u_h).to(dev)
     eo, so = torch.from_numpy(eo_h).to(dev), torch.from_numpy(so_h).to(dev)
     n, S, D = int(eo_h[-1]), int(so_h[-1]), eo_h.size - 1
-    ratio, collapsed, tuning = batch_choice(args, v, u, eo, so)
+    ratio, collapsed, tile, tuning = batch_choice(args, v, u, eo, so)
     co = rtf.cells_like(eo, ratio)
     mt = int(co[-1].item())
-    plan = BatchedPlan(eo, co, so, n, mt, S, collapsed=collapsed)
+    plan = BatchedPlan(eo, co, so, n, mt, S, collapsed=collapsed, tile=tile)
     for _ in range(args.warmup):
         plan.run(v, u)
     plan.check()
@@ -718,10 +731,10 @@ def run_c4(args):
     t_b3_gpu = event_time(per_distribution, 1)
     res = common(METRIC, "samples/s", S / (t_graph * 1e-3), t_graph, args, "u64",
                  f"C4: {D} distributions, sizes log-uniform in [16, 65536] (n_total={n}), "
-                 f"uniform or Pareto(1.2) weights, m_d={ratio:g}n_d ({tuning['source']}), "
-                 f"{'collapsed' if collapsed else 'binary'} descent, {S} uniforms (64 per 1k "
-                 "weights), quantise + build + sample with x",
-                 cell_ratio=ratio, collapsed=collapsed, tuning=tuning,
+                 f"uniform or Pareto(1.2) weights, m_d={ratio:g}n_d, {tile}-element build tiles "
+                 f"({tuning['source']}), {'collapsed' if collapsed else 'binary'} descent, {S} "
+                 "uniforms (64 per 1k weights), quantise + build + sample with x",
+                 cell_ratio=ratio, collapsed=collapsed, tile=tile, tuning=tuning,
                  elements_per_s=n / (t_graph * 1e-3), ms_eager=t_eager, ms_graph=t_graph,
                  ms_per_distribution_launches=t_b3,
                  ms_per_distribution_launches_events=t_b3_gpu,
@@ -758,7 +771,7 @@ def run_c3(args):
     xy = torch.empty(2 * pairs, dtype=torch.float64, device=dev)
     wide_ws = torch.empty(rtf.lib().rtf_wide_workspace_bytes(n), dtype=torch.uint8, device=dev)
 
-    def setup(ratio):
+    def setup(ratio, tile=2048):
         co = rtf.cells_like(eo, ratio)
         mt = int(co[-1].item())
         ws = torch.empty(rtf.lib().rtf_workspace_bytes_batched(R + 1, n, mt), dtype=torch.uint8,
@@ -767,9 +780,11 @@ def run_c3(args):
 
         def build():
             rtf.quantize(v, eo, out=(q, scale))
-            rtf._check(rtf.lib().rtf_build_batched(rtf._ptr(q), rtf._ptr(eo), rtf._ptr(co), R + 1,
-                                                   n, mt, rtf._ptr(ws), ws.numel(), rtf._stream(),
-                                                   ctypes.byref(desc)), "rtf_build_batched")
+            rtf._check(rtf.lib().rtf_build_batched_tiled(rtf._ptr(q), rtf._ptr(eo), rtf._ptr(co),
+                                                         R + 1, n, mt, tile, rtf._ptr(ws),
+                                                         ws.numel(), rtf._stream(),
+                                                         ctypes.byref(desc)),
+                       "rtf_build_batched_tiled")
         build()
         f = rtf.Forest(ws, desc, dev)
         return co, f, build
@@ -786,19 +801,27 @@ def run_c3(args):
         candidates, source = [(0.125, False), (0.25, False), (0.5, False), (0.25, True),
                               (0.5, True), (1.0, True)], "tuner"
     times = {}
-    for ratio, coll in candidates:
-        _, f, build = setup(ratio)
+
+    def try_(ratio, coll, tile):
+        _, f, build = setup(ratio, tile)
 
         def chain():
             build()
             if coll:
                 widen(f)
             sample(f)
-        times[f"{ratio}|{int(coll)}"] = tune._time_ms(chain, 3)
+        times[f"{ratio}|{int(coll)}|{tile}"] = tune._time_ms(chain, 3)
         del f
+
+    tiles = (args.tile,) if args.tile else tune.TILES
+    for ratio, coll in candidates:
+        try_(ratio, coll, tiles[0])
     best = min(times, key=times.get)
-    ratio, collapsed = float(best.split("|")[0]), bool(int(best.split("|")[1]))
-    co, f, build = setup(ratio)
+    for tile in tiles[1:]:  # the tile for the best ratio and descent form
+        try_(float(best.split("|")[0]), bool(int(best.split("|")[1])), tile)
+    best = min(times, key=times.get)
+    ratio, collapsed, tile = float(best.split("|")[0]), bool(int(best.split("|")[1])), int(best.split("|")[2])
+    co, f, build = setup(ratio, tile)
     torch.cuda.synchronize()
     f.check()
     t_build = event_time(build, args.steps)
@@ -837,10 +860,11 @@ def run_c3(args):
     ms = t_build + (t_widen + t_sample_w if collapsed else t_sample)
     res = common(METRIC, "pairs/s", pairs / (ms * 1e-3), ms, args, "u64",
                  "C3: 4096x4096 log-normal(0,1.5) map + 8 hot spots (1e4, sigma 3 px); marginal + "
-                 f"4096 rows quantised and built as one batch (m_d={ratio:g}n_d, {source}); "
+                 f"4096 rows quantised and built as one batch (m_d={ratio:g}n_d, {tile}-element "
+                 f"tiles, {source}); "
                  f"{'collapsed' if collapsed else 'binary'} descent; 2^27 (row, col) pairs + "
                  "sub-pixel positions",
-                 cell_ratio=ratio, collapsed=collapsed,
+                 cell_ratio=ratio, collapsed=collapsed, tile=tile,
                  tuning={"source": source, "ms_build_plus_sample": times},
                  ms_build=t_build, ms_sample=t_sample, ms_widen=t_widen,
                  ms_sample_collapsed=t_sample_w,
@@ -937,10 +961,10 @@ def run_c5(args):
     so = torch.arange(D + 1, dtype=torch.int64, device=dev) * per
     v = torch.nn.functional.softplus(z).reshape(-1).contiguous()
     from paper_1901_05423_amd.plan import BatchedPlan
-    ratio, collapsed, tuning = batch_choice(args, v, u, eo, so)
+    ratio, collapsed, tile, tuning = batch_choice(args, v, u, eo, so)
     md = max(1, int(round(nd * ratio)))
     co = torch.arange(D + 1, dtype=torch.int64, device=dev) * md
-    plan = BatchedPlan(eo, co, so, D * nd, D * md, D * per, collapsed=collapsed)
+    plan = BatchedPlan(eo, co, so, D * nd, D * md, D * per, collapsed=collapsed, tile=tile)
     plan.run(v, u)
     plan.check()
     f = plan
@@ -960,7 +984,7 @@ def run_c5(args):
                  f"({tuning['source']}), {'collapsed' if collapsed else 'binary'} descent, 2^20 "
                  "uniforms each; forward quantise + build + sample with x, backward dL/dw of "
                  "L = sum sin(7x)",
-                 cell_ratio=ratio, collapsed=collapsed, tuning=tuning,
+                 cell_ratio=ratio, collapsed=collapsed, tile=tile, tuning=tuning,
                  ms_forward=t_fwd, ms_backward=t_bwd,
                  forward_samples_s=S / (t_fwd * 1e-3), backward_samples_s=S / (t_bwd * 1e-3))
     print(json.dumps(res), flush=True)

@@ -151,6 +151,25 @@ rtf_status rtf_build_batched(const uint32_t *w, const int64_t *elem_off,
                              size_t ws_bytes, hipStream_t stream,
                              rtf_forest *out);
 
+/*
+ * rtf_build and rtf_build_batched with the build tile chosen by the caller
+ * (Sec. 5 leaves the work split open; the autotuner picks it per workload):
+ *   tile  elements per build tile, 1024 or 2048 (2048 is what rtf_build and
+ *         rtf_build_batched use); anything else is RTF_ERR_INVALID_ARG
+ * The forest is the same for either tile, bit for bit; only the speed
+ * differs (1024-element tiles suit batches of many small distributions).
+ * The workspace sizes above cover both tiles.  The descriptor's tile field
+ * records the choice.
+ */
+rtf_status rtf_build_tiled(const uint32_t *w, int64_t n, int64_t m, int32_t tile,
+                           void *ws, size_t ws_bytes, hipStream_t stream,
+                           rtf_forest *out);
+rtf_status rtf_build_batched_tiled(const uint32_t *w, const int64_t *elem_off,
+                                   const int64_t *cell_off, int32_t D,
+                                   int64_t n_total, int64_t m_total, int32_t tile,
+                                   void *ws, size_t ws_bytes, hipStream_t stream,
+                                   rtf_forest *out);
+
 /* ---- collapsed nodes (Sec. 2.4 k-ary trees; Sec. 5) --------------------- */
 
 /* Bytes of workspace for rtf_forest_widen of a forest with n_total nodes;

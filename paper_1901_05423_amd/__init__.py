@@ -78,6 +78,8 @@ SIGNATURES = {
     "rtf_workspace_bytes_batched": (_SZ, [_I32, _I64, _I64]),
     "rtf_build": (ctypes.c_int, [_P, _I64, _I64, _P, _SZ, _P, _FP]),
     "rtf_build_batched": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I64, _P, _SZ, _P, _FP]),
+    "rtf_build_tiled": (ctypes.c_int, [_P, _I64, _I64, _I32, _P, _SZ, _P, _FP]),
+    "rtf_build_batched_tiled": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I64, _I32, _P, _SZ, _P, _FP]),
     "rtf_wide_workspace_bytes": (_SZ, [_I64]),
     "rtf_forest_widen": (ctypes.c_int, [_FP, _P, _SZ, _P]),
     "rtf_balance_workspace_bytes": (_SZ, [_I64]),
@@ -280,9 +282,10 @@ def _workspace(nbytes, device):
     return ws
 
 
-def build(w, m: int, ws=None, stream=None) -> Forest:
+def build(w, m: int, ws=None, stream=None, tile: int = 0) -> Forest:
     """Guide table + radix tree forest of one distribution (uint32 weights).
-    ``ws`` may be a uint8 device tensor to reuse (e.g. a previous forest's)."""
+    ``ws`` may be a uint8 device tensor to reuse (e.g. a previous forest's);
+    ``tile`` (1024 or 2048; 0 for the default) sets the build tile."""
     torch = _torch()
     _dev(w, torch.int32 if w.dtype == torch.int32 else torch.uint32, "w")
     n = w.numel()
@@ -292,16 +295,21 @@ def build(w, m: int, ws=None, stream=None) -> Forest:
     if ws is None or ws.numel() < nb:
         ws = _workspace(nb, w.device)
     desc = rtf_forest()
-    _check(lib().rtf_build(_ptr(w), n, int(m), _ptr(ws), nb, _stream(stream),
-                           ctypes.byref(desc)), "rtf_build")
+    if tile:
+        _check(lib().rtf_build_tiled(_ptr(w), n, int(m), int(tile), _ptr(ws), nb, _stream(stream),
+                                     ctypes.byref(desc)), "rtf_build_tiled")
+    else:
+        _check(lib().rtf_build(_ptr(w), n, int(m), _ptr(ws), nb, _stream(stream),
+                               ctypes.byref(desc)), "rtf_build")
     return Forest(ws, desc, w.device)
 
 
-def build_batched(w, elem_off, cell_off, stream=None) -> Forest:
+def build_batched(w, elem_off, cell_off, stream=None, tile: int = 0) -> Forest:
     """Forests of D distributions in one launch sequence (Sec. 5).
 
     ``elem_off``/``cell_off`` are int64 device tensors of D+1 offsets.  The
     workspace is sized from ``w.numel()`` and ``cell_off[-1]`` (read back).
+    ``tile`` (1024 or 2048; 0 for the default) sets the build tile.
     """
     torch = _torch()
     _dev(elem_off, torch.int64, "elem_off")
@@ -314,9 +322,14 @@ def build_batched(w, elem_off, cell_off, stream=None) -> Forest:
         raise RtfError(RTF_ERR_SIZE, "rtf_workspace_bytes_batched")
     ws = _workspace(nb, w.device)
     desc = rtf_forest()
-    _check(lib().rtf_build_batched(_ptr(w), _ptr(elem_off), _ptr(cell_off), D, n_total,
-                                   m_total, _ptr(ws), nb, _stream(stream), ctypes.byref(desc)),
-           "rtf_build_batched")
+    if tile:
+        _check(lib().rtf_build_batched_tiled(_ptr(w), _ptr(elem_off), _ptr(cell_off), D, n_total,
+                                             m_total, int(tile), _ptr(ws), nb, _stream(stream),
+                                             ctypes.byref(desc)), "rtf_build_batched_tiled")
+    else:
+        _check(lib().rtf_build_batched(_ptr(w), _ptr(elem_off), _ptr(cell_off), D, n_total,
+                                       m_total, _ptr(ws), nb, _stream(stream), ctypes.byref(desc)),
+               "rtf_build_batched")
     return Forest(ws, desc, w.device)
 
 

@@ -3,6 +3,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "rtf_internal.h"
 
 using namespace rtf;
@@ -18,9 +20,16 @@ struct Layout {
     int64_t ntiles;
 };
 
+// Per-tile arrays are sized for the smaller tile (more tiles) and the
+// deferral list for whichever tile shape needs more slots, so that one
+// workspace size serves every tile shape.
+int64_t ntiles_of(int64_t n, int tile) { return (n + tile - 1) / tile; }
+
 Layout make_layout(int32_t D, int64_t n, int64_t m) {
     Layout L;
-    L.ntiles = (n + TILE - 1) / TILE;
+    L.ntiles = ntiles_of(n, Tile1024::TILE);
+    const int64_t defer_slots = std::max(L.ntiles * Tile1024::DEFER_CAP,
+                                         ntiles_of(n, Tile2048::TILE) * Tile2048::DEFER_CAP);
     size_t o = 0;
     L.status = o;
     o = align256(o + 256);
@@ -45,7 +54,7 @@ Layout make_layout(int32_t D, int64_t n, int64_t m) {
     L.dcnt = o;
     o = align256(o + sizeof(int32_t) * (size_t)L.ntiles);
     L.ditems = o;
-    o = align256(o + sizeof(int32_t) * (size_t)L.ntiles * DEFER_CAP);
+    o = align256(o + sizeof(int32_t) * (size_t)defer_slots);
     L.runs = o;
     o = align256(o + sizeof(Run) * (size_t)run_cap(m));
     L.total = o;
@@ -64,9 +73,11 @@ bool aligned(const T *p, size_t a) {
 rtf_status from_hip(hipError_t e) { return e == hipSuccess ? RTF_OK : RTF_ERR_HIP; }
 
 rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_t *cell_off,
-                        int32_t D, int64_t n, int64_t m, void *ws, size_t ws_bytes,
+                        int32_t D, int64_t n, int64_t m, int32_t tile, void *ws, size_t ws_bytes,
                         hipStream_t st, rtf_forest *out) {
     if (!w || !ws || !out || !aligned(w, 4) || !aligned(ws, 256)) return RTF_ERR_INVALID_ARG;
+    if (tile == 0) tile = TILE_DEFAULT;
+    if (tile != Tile1024::TILE && tile != Tile2048::TILE) return RTF_ERR_INVALID_ARG;
     if (D > 1 && (!elem_off || !cell_off || !aligned(elem_off, 8) || !aligned(cell_off, 8)))
         return RTF_ERR_INVALID_ARG;
     if (n < 1 || m < 1 || D < 1) return RTF_ERR_INVALID_ARG;
@@ -77,7 +88,7 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     rtf_forest f;
     memset(&f, 0, sizeof f);
     f.D = D;
-    f.tile = TILE;
+    f.tile = tile;
     f.n_total = n;
     f.m_total = m;
     f.nodes = b + L.nodes;
@@ -98,7 +109,8 @@ rtf_status build_common(const uint32_t *w, const int64_t *elem_off, const int64_
     a.D = D;
     a.n_total = n;
     a.m_total = m;
-    a.ntiles = L.ntiles;
+    a.tile = tile;
+    a.ntiles = ntiles_of(n, tile);
     a.nodes = static_cast<Node *>(f.nodes);
     a.cells = static_cast<Cell *>(f.cells);
     a.dists = static_cast<Dist *>(f.dists);
@@ -161,18 +173,33 @@ size_t rtf_workspace_bytes_batched(int32_t D, int64_t n_total, int64_t m_total) 
 
 rtf_status rtf_build(const uint32_t *w, int64_t n, int64_t m, void *ws, size_t ws_bytes,
                      hipStream_t stream, rtf_forest *out) {
-    return build_common(w, nullptr, nullptr, 1, n, m, ws, ws_bytes, stream, out);
+    return build_common(w, nullptr, nullptr, 1, n, m, 0, ws, ws_bytes, stream, out);
+}
+
+rtf_status rtf_build_tiled(const uint32_t *w, int64_t n, int64_t m, int32_t tile, void *ws,
+                           size_t ws_bytes, hipStream_t stream, rtf_forest *out) {
+    if (tile == 0) return RTF_ERR_INVALID_ARG;
+    return build_common(w, nullptr, nullptr, 1, n, m, tile, ws, ws_bytes, stream, out);
+}
+
+rtf_status rtf_build_batched_tiled(const uint32_t *w, const int64_t *elem_off,
+                                   const int64_t *cell_off, int32_t D, int64_t n_total,
+                                   int64_t m_total, int32_t tile, void *ws, size_t ws_bytes,
+                                   hipStream_t stream, rtf_forest *out) {
+    if (D < 1 || !elem_off || !cell_off || tile == 0) return RTF_ERR_INVALID_ARG;
+    if (D == 1) {
+        // offsets still copied so that the descriptor is self-contained
+        if (!aligned(elem_off, 8) || !aligned(cell_off, 8)) return RTF_ERR_INVALID_ARG;
+    }
+    return build_common(w, elem_off, cell_off, D, n_total, m_total, tile, ws, ws_bytes, stream,
+                        out);
 }
 
 rtf_status rtf_build_batched(const uint32_t *w, const int64_t *elem_off, const int64_t *cell_off,
                              int32_t D, int64_t n_total, int64_t m_total, void *ws,
                              size_t ws_bytes, hipStream_t stream, rtf_forest *out) {
-    if (D < 1 || !elem_off || !cell_off) return RTF_ERR_INVALID_ARG;
-    if (D == 1) {
-        // offsets still copied so that the descriptor is self-contained
-        if (!aligned(elem_off, 8) || !aligned(cell_off, 8)) return RTF_ERR_INVALID_ARG;
-    }
-    return build_common(w, elem_off, cell_off, D, n_total, m_total, ws, ws_bytes, stream, out);
+    return rtf_build_batched_tiled(w, elem_off, cell_off, D, n_total, m_total, TILE_DEFAULT, ws,
+                                   ws_bytes, stream, out);
 }
 
 size_t rtf_wide_workspace_bytes(int64_t n_total) {
@@ -407,7 +434,7 @@ rtf_status rtf_forest_import(const void *h_nodes, const void *h_cells, const uin
     rtf_forest f;
     memset(&f, 0, sizeof f);
     f.D = D;
-    f.tile = TILE;
+    f.tile = TILE_DEFAULT;
     f.n_total = n_total;
     f.m_total = m_total;
     f.nodes = b + L.nodes;

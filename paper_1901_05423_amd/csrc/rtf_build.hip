@@ -118,7 +118,7 @@ __device__ inline int32_t lower_bound(const int64_t *off, int32_t D, int64_t i) 
 // load reads a clamped, in-range index and the value is masked; neither form
 // branches, so the compiler need not wait for a load at a branch join and
 // several loads stay in flight.
-template <bool FULL>
+template <int ITEMS, bool FULL>
 __device__ inline void load_items(const uint32_t *w, int64_t i0, int64_t n, uint32_t *r) {
     static_assert(ITEMS == 2 || ITEMS % 4 == 0, "vector loads of 8 or 16 bytes");
     if constexpr (FULL) {
@@ -265,7 +265,6 @@ __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t 
 // ---------------------------------------------------------------------------
 // Each block sums TS_TILES tiles whose loads are all issued before the first
 // reduction, so that enough bytes are in flight to stream at HBM rate.
-constexpr int TS_TILES = 4;
 
 __device__ inline uint64_t wave_sum(uint64_t x) {
 #pragma unroll
@@ -273,15 +272,16 @@ __device__ inline uint64_t wave_sum(uint64_t x) {
     return x;
 }
 
-template <bool BATCHED, bool FULL>
+template <class T, bool BATCHED, bool FULL>
 __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *s_wave,
                                       uint64_t *s_thr, int32_t *s_first) {
+    constexpr int BT = T::BT, ITEMS = T::ITEMS, TILE = T::TILE, TS_TILES = T::TS_TILES;
     constexpr int NW = BT / 64;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     uint32_t r[TS_TILES][ITEMS];
 #pragma unroll
     for (int k = 0; k < TS_TILES; ++k)
-        load_items<FULL>(a.w, (t0 + k) * TILE + (int64_t)tid * ITEMS, a.n_total, r[k]);
+        load_items<ITEMS, FULL>(a.w, (t0 + k) * TILE + (int64_t)tid * ITEMS, a.n_total, r[k]);
     uint64_t sum[TS_TILES];
 #pragma unroll
     for (int k = 0; k < TS_TILES; ++k) {
@@ -357,8 +357,9 @@ __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *
     }
 }
 
-template <bool BATCHED>
-__global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
+template <class T, bool BATCHED>
+__global__ __launch_bounds__(T::BT) void k_tile_sums(BuildArgs a, bool vec) {
+    constexpr int BT = T::BT, TILE = T::TILE, TS_TILES = T::TS_TILES;
     __shared__ uint64_t s_wave[TS_TILES * (BT / 64)];
     __shared__ uint64_t s_thr[BT];
     __shared__ int32_t s_first[TS_TILES];
@@ -377,8 +378,8 @@ __global__ __launch_bounds__(BT) void k_tile_sums(BuildArgs a, bool vec) {
         }
     }
     if (vec && (t0 + TS_TILES) * TILE <= a.n_total)
-        tile_sums_body<BATCHED, true>(a, t0, s_wave, s_thr, s_first);
-    else tile_sums_body<BATCHED, false>(a, t0, s_wave, s_thr, s_first);
+        tile_sums_body<T, BATCHED, true>(a, t0, s_wave, s_thr, s_first);
+    else tile_sums_body<T, BATCHED, false>(a, t0, s_wave, s_thr, s_first);
 }
 
 // ---------------------------------------------------------------------------
@@ -391,8 +392,9 @@ constexpr int PT = 1024;
 
 // Distribution d's parameters: the total W, the divisor normalisation and
 // reciprocal, and the global prefix at its first element.
-template <bool BATCHED>
+template <class T, bool BATCHED>
 __device__ inline void dist_params_of(const BuildArgs &a, int32_t d, uint64_t total) {
+    constexpr int TILE = T::TILE;
     const int64_t eo = a.elem_off[d], e1 = a.elem_off[d + 1];
     uint64_t G0 = 0, G1 = total;
     if (BATCHED) {
@@ -421,7 +423,7 @@ __device__ inline void dist_params_of(const BuildArgs &a, int32_t d, uint64_t to
     a.dists[d] = P;
 }
 
-template <bool BATCHED>
+template <class T, bool BATCHED>
 __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
     __shared__ uint64_t s_wave[PT / 64];
     const int64_t nt = a.ntiles;
@@ -462,13 +464,13 @@ __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
     }
     __threadfence_block();
     __syncthreads();
-    if ((int32_t)threadIdx.x < a.D) dist_params_of<BATCHED>(a, (int32_t)threadIdx.x, total);
+    if ((int32_t)threadIdx.x < a.D) dist_params_of<T, BATCHED>(a, (int32_t)threadIdx.x, total);
 }
 
-template <bool BATCHED>
+template <class T, bool BATCHED>
 __global__ __launch_bounds__(256) void k_dist_finish(BuildArgs a) {
     const int32_t d = (int32_t)(blockIdx.x * 256 + threadIdx.x);
-    if (d < a.D) dist_params_of<BATCHED>(a, d, a.tile_prefix[a.ntiles]);
+    if (d < a.D) dist_params_of<T, BATCHED>(a, d, a.tile_prefix[a.ntiles]);
 }
 
 // ---------------------------------------------------------------------------
@@ -492,14 +494,10 @@ __global__ __launch_bounds__(256) void k_dist_finish(BuildArgs a) {
 // inside the tile are 32-bit: local leaf li is global leaf lb0 + li, local
 // boundary bi lies between local leaves bi and bi + 1 (it is node bi + 1).
 // ---------------------------------------------------------------------------
-constexpr int LEAF_N = TILE + 2 * HALO;
-constexpr int LVL_N = LEAF_N - 1;  // real boundaries; lvl[LVL_N] is padding
-static_assert(LEAF_N % 8 == 0, "levels are read 8 at a time");
 static_assert(2 * HALO == 64, "wave 0 loads both halos, one leaf per lane");
 // Child slots hold local node indices (16 bits) and window entries 16-bit
 // owner codes, so that the tile's LDS (about 38 KB) lets four blocks share a
 // CU.
-static_assert(WIN % 8 == 0 && (2 * TILE) % 8 == 0, "16-byte clears of slot and window");
 // An empty child slot holds -1 in LDS and reads as SLOT_EMPTY, never a node
 // or leaf reference.
 constexpr int32_t SLOT_EMPTY = INT32_MIN;
@@ -511,30 +509,37 @@ constexpr uint16_t WIN_ROOT = 0 << 14;  // the cell's first node
 constexpr uint16_t WIN_HEAD = 1 << 14;  // covered by the leaf before that node
 constexpr uint16_t WIN_TAIL = 2 << 14;  // covered by a distribution's last leaf
 constexpr uint16_t WIN_KIND = 0xC000, WIN_LEAF = 0x3FFF;
-static_assert(LEAF_N <= WIN_LEAF, "local leaf indices fit an owner code");
-
+template <class T>
 struct alignas(16) TileSmem {
+    static constexpr int LEAF_N = T::TILE + 2 * HALO;
+    static constexpr int LVL_N = LEAF_N - 1;  // real boundaries; lvl[LVL_N] is padding
+    static_assert(LEAF_N % 8 == 0, "levels are read 8 at a time");
+    static_assert(T::WIN % 8 == 0 && (2 * T::TILE) % 8 == 0, "16-byte clears of slot and window");
+    static_assert(LEAF_N <= WIN_LEAF, "local leaf indices fit an owner code");
+    static_assert(2 * T::TILE <= 32767, "local node indices fit a 16-bit slot");
     uint64_t key[LEAF_N];
     int32_t cell[LEAF_N];
-    int16_t slot[2 * TILE];  // child slots of the tile's own nodes (local node index)
-    uint16_t win[WIN];       // owner codes of cells c_begin .. c_begin + WIN - 1
+    int16_t slot[2 * T::TILE];  // child slots of the tile's own nodes (local node index)
+    uint16_t win[T::WIN];       // owner codes of cells c_begin .. c_begin + WIN - 1
     uint64_t lvl8[LEAF_N / 8];
-    uint64_t wave[BT / 64];
+    uint64_t wave[T::BT / 64];
     int64_t c_begin;
     int32_t win_hi;  // highest window position phase 4 wrote
     int32_t ndefer;
     int32_t item_base;  // this tile's place in the grid-wide deferral list
-    int32_t items[DEFER_CAP];
+    int32_t items[T::DEFER_CAP];
 };
 
-__device__ inline void push_item(TileSmem &sm, int32_t item) {
+template <class T>
+__device__ inline void push_item(TileSmem<T> &sm, int32_t item) {
     int32_t k = atomicAdd(&sm.ndefer, 1);
-    if (k < DEFER_CAP) sm.items[k] = item;
+    if (k < T::DEFER_CAP) sm.items[k] = item;
 }
 
 // the level of local boundary bi: byte bi of the level array (one LDS byte
 // read, no shift)
-__device__ inline int lvl_at(const TileSmem &sm, int bi) {
+template <class T>
+__device__ inline int lvl_at(const TileSmem<T> &sm, int bi) {
     return reinterpret_cast<const uint8_t *>(sm.lvl8)[bi];
 }
 
@@ -551,7 +556,8 @@ __device__ inline uint64_t ge_mask(uint64_t w, int t) {
 constexpr int SCAN_WORDS = SCAN_CAP / 8;
 
 // nearest boundary at or left of bi with a level >= t, or -1
-__device__ inline int nearest_ge_left(const TileSmem &sm, int bi, int t) {
+template <class T>
+__device__ inline int nearest_ge_left(const TileSmem<T> &sm, int bi, int t) {
     if (bi < 0) return -1;
     int wi = bi >> 3;
     const int pos = bi & 7;
@@ -565,7 +571,9 @@ __device__ inline int nearest_ge_left(const TileSmem &sm, int bi, int t) {
 }
 
 // nearest boundary at or right of bi with a level >= t, or -1
-__device__ inline int nearest_ge_right(const TileSmem &sm, int bi, int t) {
+template <class T>
+__device__ inline int nearest_ge_right(const TileSmem<T> &sm, int bi, int t) {
+    constexpr int LEAF_N = TileSmem<T>::LEAF_N, LVL_N = TileSmem<T>::LVL_N;
     if (bi >= LVL_N) return -1;
     int wi = bi >> 3;
     uint64_t m = ge_mask(sm.lvl8[wi], t) & (~0ull << (8 * (bi & 7)));
@@ -579,13 +587,15 @@ __device__ inline int nearest_ge_right(const TileSmem &sm, int bi, int t) {
 
 // write local node `child` into child slot `side` of local node pn if the
 // tile owns it
-__device__ inline void link(TileSmem &sm, int pn, int side, int child) {
+template <class T>
+__device__ inline void link(TileSmem<T> &sm, int pn, int side, int child) {
     const int s = pn - HALO;
-    if (s >= 0 && s < TILE) sm.slot[2 * s + side] = (int16_t)child;
+    if (s >= 0 && s < T::TILE) sm.slot[2 * s + side] = (int16_t)child;
 }
 
 // child slot k as a global reference (SLOT_EMPTY when nothing was linked)
-__device__ inline int32_t slot_ref(const TileSmem &sm, int k, int32_t lb0) {
+template <class T>
+__device__ inline int32_t slot_ref(const TileSmem<T> &sm, int k, int32_t lb0) {
     const int16_t v = sm.slot[k];
     return v < 0 ? SLOT_EMPTY : lb0 + v;
 }
@@ -593,9 +603,10 @@ __device__ inline int32_t slot_ref(const TileSmem &sm, int k, int32_t lb0) {
 // stage the record of cell c (owner code w) in the window, or store it
 // directly when the cell lies past the window
 // (returns the window position written, or -1)
-__device__ inline int put_cell(TileSmem &sm, Cell *cells, int64_t c, uint16_t w, int32_t lb0) {
+template <class T>
+__device__ inline int put_cell(TileSmem<T> &sm, Cell *cells, int64_t c, uint16_t w, int32_t lb0) {
     const int64_t x = c - sm.c_begin;
-    if (x >= 0 && x < WIN) {
+    if (x >= 0 && x < T::WIN) {
         sm.win[x] = w;
         return (int)x;
     }
@@ -606,7 +617,8 @@ __device__ inline int put_cell(TileSmem &sm, Cell *cells, int64_t c, uint16_t w,
     return -1;
 }
 
-__device__ inline void root_cell_record(const TileSmem &sm, Cell *cells, int64_t c, int li,
+template <class T>
+__device__ inline void root_cell_record(const TileSmem<T> &sm, Cell *cells, int64_t c, int li,
                                         int32_t lb0) {
     uint64_t key[CELL_BOUNDS + 1];
     int32_t cell[CELL_BOUNDS + 1];
@@ -626,8 +638,9 @@ __device__ inline void root_cell_record(const TileSmem &sm, Cell *cells, int64_t
 // distribution parameters) is issued before the block scan and none sits
 // under a branch, so a block waits for one round trip.  FULL: the tile lies
 // inside [0, n) and the weights are 16-byte aligned.
-template <bool BATCHED, bool FULL, bool UNI>
-__device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
+template <class T, bool BATCHED, bool FULL, bool UNI>
+__device__ inline void build_keys(const BuildArgs &a, TileSmem<T> &sm, int64_t t) {
+    constexpr int BT = T::BT, ITEMS = T::ITEMS, TILE = T::TILE;
     const int tid = threadIdx.x;
     const int64_t base = t * TILE;
     const int64_t n = a.n_total;
@@ -642,7 +655,7 @@ __device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
     const int64_t i0 = base + (int64_t)tid * ITEMS;
     const int li0 = HALO + tid * ITEMS;
     uint32_t wv[ITEMS];
-    load_items<FULL>(a.w, i0, n, wv);
+    load_items<T::ITEMS, FULL>(a.w, i0, n, wv);
     const uint64_t tp = a.tile_prefix[t];
     // the distributions of the tile's elements lie in [d_lo, d_hi]; UNI: in
     // one distribution, whose parameters are then uniform (scalar registers)
@@ -705,13 +718,17 @@ __device__ inline void build_keys(const BuildArgs &a, TileSmem &sm, int64_t t) {
     }
 }
 
-// The LDS allows four blocks per CU.  The single-distribution instance fits
-// 64 registers and runs four (eight waves per SIMD); the batched instance,
-// which needs more, is held to 80 registers for three blocks, at the price
-// of a few spilled ones.
-template <bool BATCHED>
-__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(BATCHED ? 6 : 8))) void k_build_tile(BuildArgs a, bool vec) {
-    __shared__ TileSmem sm;
+// With 2048-element tiles the LDS allows four blocks per CU.  The
+// single-distribution instance fits 64 registers and runs four (eight waves
+// per SIMD); the batched instance, which needs more, is held to 80 registers
+// for three blocks, at the price of a few spilled ones.  With 1024-element
+// tiles of 256 threads the LDS allows seven blocks, and the batched instance
+// fits its 80 registers without spills.
+template <class T, bool BATCHED>
+__global__ __launch_bounds__(T::BT) __attribute__((amdgpu_waves_per_eu(BATCHED ? T::WAVES_BATCHED : T::WAVES_ONE))) void k_build_tile(BuildArgs a, bool vec) {
+    constexpr int BT = T::BT, TILE = T::TILE, WIN = T::WIN, DEFER_CAP = T::DEFER_CAP;
+    constexpr int LEAF_N = TileSmem<T>::LEAF_N, LVL_N = TileSmem<T>::LVL_N;
+    __shared__ TileSmem<T> sm;
     const int tid = threadIdx.x;
     const int64_t t = blockIdx.x;
     const int64_t base = t * TILE;
@@ -726,11 +743,11 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(BATCHED ? 6 
     // uniform parameters
     const bool full = vec && base + TILE <= n;
     if (!BATCHED || d_lo == d_hi) {
-        if (full) build_keys<BATCHED, true, true>(a, sm, t);
-        else build_keys<BATCHED, false, true>(a, sm, t);
+        if (full) build_keys<T, BATCHED, true, true>(a, sm, t);
+        else build_keys<T, BATCHED, false, true>(a, sm, t);
     } else {
-        if (full) build_keys<BATCHED, true, false>(a, sm, t);
-        else build_keys<BATCHED, false, false>(a, sm, t);
+        if (full) build_keys<T, BATCHED, true, false>(a, sm, t);
+        else build_keys<T, BATCHED, false, false>(a, sm, t);
     }
     __syncthreads();
 
@@ -1108,7 +1125,7 @@ struct GlobalView {
     }
 };
 
-template <bool BATCHED>
+template <class T, bool BATCHED>
 __device__ void fixup_tile(const BuildArgs &a, int64_t t);
 
 // The deferred nodes of all tiles are one list: while it is short, each
@@ -1117,8 +1134,9 @@ __device__ void fixup_tile(const BuildArgs &a, int64_t t);
 // deferral counts of a contiguous range of tiles in parallel and redoes, one
 // thread per node, a tile that deferred more than it could list.  Then every
 // wave fills an equal share of the cells of the listed guide-table runs.
-template <bool BATCHED>
-__global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
+template <class T, bool BATCHED>
+__global__ __launch_bounds__(T::BT) void k_fixup(BuildArgs a) {
+    constexpr int BT = T::BT, TILE = T::TILE, DEFER_CAP = T::DEFER_CAP;
     constexpr int NW = BT / 64;
     __shared__ int32_t s_list[BT];
     __shared__ int32_t s_nt;
@@ -1161,7 +1179,7 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
         if (t < t_hi && a.defer_count[t] > DEFER_CAP) s_list[atomicAdd(&s_nt, 1)] = tid;
         __syncthreads();
         const int32_t nt = s_nt;
-        for (int32_t q = 0; q < nt; ++q) fixup_tile<BATCHED>(a, t0 + s_list[q]);
+        for (int32_t q = 0; q < nt; ++q) fixup_tile<T, BATCHED>(a, t0 + s_list[q]);
         __syncthreads();
     }
     // the listed cells [0, total) in equal contiguous shares, one per wave
@@ -1195,8 +1213,9 @@ __global__ __launch_bounds__(BT) void k_fixup(BuildArgs a) {
     }
 }
 
-template <bool BATCHED>
+template <class T, bool BATCHED>
 __device__ void fixup_tile(const BuildArgs &a, int64_t t) {
+    constexpr int BT = T::BT, TILE = T::TILE;
     // more deferrals than a tile lists: redo every node record of the tile
     const int64_t base = t * TILE;
     const int32_t d_lo = BATCHED ? a.tile_dist[t] : 0, d_hi = BATCHED ? a.tile_dist[t + 1] : 0;
@@ -1504,24 +1523,31 @@ hipError_t launch_balance(Node *nodes, Cell *cells, const Dist *dists, const int
     return hipGetLastError();
 }
 
-hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
+template <class T>
+void enqueue_build(const BuildArgs &a, hipStream_t st) {
+    constexpr int BT = T::BT;
     const bool vec = (reinterpret_cast<uintptr_t>(a.w) & 15) == 0;
     const dim3 grid((unsigned)a.ntiles);
-    const dim3 sumgrid((unsigned)((a.ntiles + TS_TILES - 1) / TS_TILES));
+    const dim3 sumgrid((unsigned)((a.ntiles + T::TS_TILES - 1) / T::TS_TILES));
     const dim3 fixgrid((unsigned)(a.ntiles < 1024 ? a.ntiles : 1024));
     if (a.D > 1) {
-        hipLaunchKernelGGL(k_tile_sums<true>, sumgrid, dim3(BT), 0, st, a, vec);
-        hipLaunchKernelGGL(k_dist_params<true>, dim3(1), dim3(PT), 0, st, a);
+        hipLaunchKernelGGL((k_tile_sums<T, true>), sumgrid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL((k_dist_params<T, true>), dim3(1), dim3(PT), 0, st, a);
         if (a.D > PT)
-            hipLaunchKernelGGL(k_dist_finish<true>, dim3((unsigned)((a.D + 255) / 256)), dim3(256), 0, st, a);
-        hipLaunchKernelGGL(k_build_tile<true>, grid, dim3(BT), 0, st, a, vec);
-        hipLaunchKernelGGL(k_fixup<true>, fixgrid, dim3(BT), 0, st, a);
+            hipLaunchKernelGGL((k_dist_finish<T, true>), dim3((unsigned)((a.D + 255) / 256)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_build_tile<T, true>), grid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL((k_fixup<T, true>), fixgrid, dim3(BT), 0, st, a);
     } else {
-        hipLaunchKernelGGL(k_tile_sums<false>, sumgrid, dim3(BT), 0, st, a, vec);
-        hipLaunchKernelGGL(k_dist_params<false>, dim3(1), dim3(PT), 0, st, a);
-        hipLaunchKernelGGL(k_build_tile<false>, grid, dim3(BT), 0, st, a, vec);
-        hipLaunchKernelGGL(k_fixup<false>, fixgrid, dim3(BT), 0, st, a);
+        hipLaunchKernelGGL((k_tile_sums<T, false>), sumgrid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL((k_dist_params<T, false>), dim3(1), dim3(PT), 0, st, a);
+        hipLaunchKernelGGL((k_build_tile<T, false>), grid, dim3(BT), 0, st, a, vec);
+        hipLaunchKernelGGL((k_fixup<T, false>), fixgrid, dim3(BT), 0, st, a);
     }
+}
+
+hipError_t launch_build(const BuildArgs &a, hipStream_t st) {
+    if (a.tile == Tile1024::TILE) enqueue_build<Tile1024>(a, st);
+    else enqueue_build<Tile2048>(a, st);
     return hipGetLastError();
 }
 

@@ -13,14 +13,33 @@ namespace rtf {
 // weights that carry mass (Alg. 1 sets the neighbour "to the maximum").
 constexpr int SENT = 65;
 
-// Build tile: 512 threads x 4 consecutive elements.
-constexpr int BT = 512;
-constexpr int ITEMS = 4;
-constexpr int TILE = BT * ITEMS;
-// Guide cells staged in LDS per tile before their coalesced store.  With m
-// proportional to n a tile's records fall in about m/n * TILE consecutive
-// cells; records past the window are stored directly.
-constexpr int WIN = TILE + 128;
+// Build tile shapes: BT threads x ITEMS consecutive elements per block.  The
+// forest does not depend on the shape, only the speed does: 2048-element
+// tiles of 512 threads suit one large distribution; batches of many uneven
+// distributions build faster in 1024-element tiles of 256 threads, whose
+// batched kernel then fits its registers without spills.
+template <int BT_, int ITEMS_, int WAVES_ONE_, int WAVES_BATCHED_>
+struct Tiling {
+    static constexpr int BT = BT_;
+    static constexpr int ITEMS = ITEMS_;
+    // waves per SIMD the tile kernel is compiled for, one distribution and
+    // batched (the batched instance needs more registers); the LDS of one
+    // tile bounds it too
+    static constexpr int WAVES_ONE = WAVES_ONE_;
+    static constexpr int WAVES_BATCHED = WAVES_BATCHED_;
+    static constexpr int TILE = BT * ITEMS;
+    // Guide cells staged in LDS per tile before their coalesced store.  With
+    // m proportional to n a tile's records fall in about m/n * TILE
+    // consecutive cells; records past the window are stored directly.
+    static constexpr int WIN = TILE + 128;
+    // Deferred node records kept per tile; more make the fix-up redo the tile.
+    static constexpr int DEFER_CAP = TILE / 16;
+    // Tiles summed per block of the tile-sum pass (one wave per search there).
+    static constexpr int TS_TILES = BT / 128;
+};
+using Tile2048 = Tiling<512, 4, 8, 6>;  // 40 KB of LDS per tile: four per CU
+using Tile1024 = Tiling<256, 4, 7, 6>;  // 21 KB: seven per CU
+constexpr int TILE_DEFAULT = Tile2048::TILE;
 // Leaves on either side of a tile whose keys are recomputed locally so that
 // subtree scans near the tile edges stay in LDS.
 constexpr int HALO = 32;
@@ -29,8 +48,6 @@ constexpr int SCAN_CAP = 64;
 // Longest guide-table run written by one lane; a longer run is listed for the
 // fix-up kernel, whose waves split the listed runs' cells evenly.
 constexpr int RUN_CAP = 64;
-// Deferred node records kept per tile; more make the fix-up redo the tile.
-constexpr int DEFER_CAP = 128;
 
 struct alignas(16) Node {
     uint64_t key;
@@ -122,6 +139,7 @@ struct BuildArgs {
     int32_t D;
     int64_t n_total;
     int64_t m_total;
+    int32_t tile;                 // elements per tile: Tile2048::TILE or Tile1024::TILE
     int64_t ntiles;
     Node *nodes;
     Cell *cells;
@@ -133,7 +151,7 @@ struct BuildArgs {
     int32_t *defer_count;   // [ntiles]
     int32_t *defer_items;   // [ntiles * DEFER_CAP]: the deferred nodes of all tiles, one list
     uint32_t *item_count;   // length of that list
-    int32_t *tile_dist;     // [ntiles + 2]: distribution of element min(t TILE, n - 1)
+    int32_t *tile_dist;     // [ntiles + 2]: distribution of element min(t tile, n - 1)
     uint64_t *run_count;    // (runs listed << 32) | cells they cover
     Run *runs;              // [run_cap(m_total)]
 };

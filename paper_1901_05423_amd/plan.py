@@ -24,8 +24,9 @@ class BatchedPlan:
     """
 
     def __init__(self, elem_off, cell_off, sample_off, n_total, m_total, S, want_x=True,
-                 collapsed=False):
+                 collapsed=False, tile=0):
         dev = elem_off.device
+        self.tile = int(tile) or 2048  # elements per build tile (1024 or 2048)
         self.D = elem_off.numel() - 1
         self.elem_off, self.cell_off, self.sample_off = elem_off, cell_off, sample_off
         self.n, self.m, self.S = int(n_total), int(m_total), int(S)
@@ -53,9 +54,10 @@ class BatchedPlan:
         st = _stream(stream)
         _check(L.rtf_quantize_f32(_ptr(v), _ptr(self.elem_off), self.D, self.n, _ptr(self.q),
                                   _ptr(self.scale), _ptr(self.status), st), "rtf_quantize_f32")
-        _check(L.rtf_build_batched(_ptr(self.q), _ptr(self.elem_off), _ptr(self.cell_off),
-                                   self.D, self.n, self.m, _ptr(self.ws), self.ws_bytes, st,
-                                   ctypes.byref(self.desc)), "rtf_build_batched")
+        _check(L.rtf_build_batched_tiled(_ptr(self.q), _ptr(self.elem_off), _ptr(self.cell_off),
+                                         self.D, self.n, self.m, self.tile, _ptr(self.ws),
+                                         self.ws_bytes, st, ctypes.byref(self.desc)),
+               "rtf_build_batched_tiled")
         if self.collapsed:
             _check(L.rtf_forest_widen(ctypes.byref(self.desc), _ptr(self.wide_ws),
                                       self.wide_ws.numel(), st), "rtf_forest_widen")
@@ -100,9 +102,9 @@ class DiffPlan(BatchedPlan):
     """
 
     def __init__(self, elem_off, cell_off, sample_off, n_total, m_total, S, v_dtype=torch.float32,
-                 collapsed=False):
+                 collapsed=False, tile=0):
         super().__init__(elem_off, cell_off, sample_off, n_total, m_total, S, want_x=True,
-                         collapsed=collapsed)
+                         collapsed=collapsed, tile=tile)
         L = lib()
         dev = elem_off.device
         self.bws_bytes = L.rtf_backward_workspace_bytes(self.D, self.n)

@@ -1,12 +1,14 @@
-"""Autotuner for the guide-table size and the descent form.
+"""Autotuner for the guide-table size, the build tile and the descent form.
 
-The sampled indices do not depend on the number of guide cells m; only speed
-does.  The paper leaves m open ("as much memory as affordable, or
-proportional to n", Sec. 3).  More cells let more samples finish in one
-cell record, but a larger table costs build bytes and cache capacity.
-`best_cell_ratio` times build + sample for candidate ratios m/n on the
-caller's own data and shape, and remembers the winner in a JSON cache keyed
-by the device architecture and the size bucket (log2 of n and of S/n).
+The sampled indices do not depend on the number of guide cells m, nor on the
+build tile; only speed does.  The paper leaves m open ("as much memory as
+affordable, or proportional to n", Sec. 3).  More cells let more samples
+finish in one cell record, but a larger table costs build bytes and cache
+capacity.  Batches of many small distributions build faster in 1024-element
+tiles, one large distribution in 2048-element ones.  `best_cell_ratio` and
+`best_batched` time the candidates on the caller's own data and shape, and
+remember the winner in a JSON cache keyed by the device architecture and the
+size bucket (log2 of n and of S/n).
 
 Environment: RTF_CELL_RATIO forces a ratio; RTF_TUNE_CACHE names the cache
 file (default ~/.cache/rtforest/tune.json).
@@ -112,17 +114,28 @@ def best_cell_ratio(w, u, candidates=CANDIDATES, use_cache=True, reps=5, with_ti
 
 
 BATCH_CANDIDATES = tuple((r, c) for r in (0.125, 0.25, 0.5, 1.0) for c in (False, True))
+TILES = (2048, 1024)
+
+
+def best_tile(run, tiles=TILES, reps=5):
+    """(tile, times): the build tile for which run(tile), a whole build +
+    sample enqueued on the current stream, is fastest; times maps each tile
+    to ms."""
+    times = {int(tl): _time_ms(lambda: run(tl), reps) for tl in tiles}
+    return min(times, key=times.get), {str(k): v for k, v in times.items()}
 
 
 def best_batched(v, u, elem_off, sample_off, candidates=BATCH_CANDIDATES, use_cache=True,
-                 reps=5, key_extra=""):
-    """(ratio, collapsed, times) with the fastest quantise + build (+ collapse)
-    + sample of the batch: v float32 weights, u uint64 uniforms, elem_off and
-    sample_off int64 device offsets (D+1).  times maps "ratio|collapsed" to ms
-    ({} when the choice came from the environment or the cache)."""
+                 reps=5, key_extra="", tiles=TILES):
+    """(ratio, collapsed, tile, times) with the fastest quantise + build (+
+    collapse) + sample of the batch: v float32 weights, u uint64 uniforms,
+    elem_off and sample_off int64 device offsets (D+1).  The ratio and the
+    descent form are chosen first with the default tile, then the tile for
+    them.  times maps "ratio|collapsed|tile" to ms ({} when the choice came
+    from the environment or the cache)."""
     forced = forced_ratio()
     if forced is not None:
-        return forced, False, {}
+        return forced, False, tiles[0], {}
     from . import cells_like
     from .plan import BatchedPlan
     D = elem_off.numel() - 1
@@ -131,16 +144,26 @@ def best_batched(v, u, elem_off, sample_off, candidates=BATCH_CANDIDATES, use_ca
                      n, S)
     cache = load_cache() if use_cache else {}
     if key in cache:
-        return float(cache[key]["ratio"]), bool(cache[key]["collapsed"]), {}
+        e = cache[key]
+        return float(e["ratio"]), bool(e["collapsed"]), int(e.get("tile", tiles[0])), {}
     times = {}
-    for r, c in candidates:
+
+    def run(r, c, tile):
         co = cells_like(elem_off, r)
-        plan = BatchedPlan(elem_off, co, sample_off, n, int(co[-1].item()), S, collapsed=c)
-        times[f"{r}|{int(c)}"] = _time_ms(lambda: plan.run(v, u), reps)
+        plan = BatchedPlan(elem_off, co, sample_off, n, int(co[-1].item()), S, collapsed=c,
+                           tile=tile)
+        times[f"{r}|{int(c)}|{tile}"] = _time_ms(lambda: plan.run(v, u), reps)
         del plan
+
+    for r, c in candidates:
+        run(r, c, tiles[0])
     best = min(times, key=times.get)
-    r, c = best.split("|")
+    r, c, _ = best.split("|")
+    for tile in tiles[1:]:
+        run(float(r), bool(int(c)), tile)
+    best = min(times, key=times.get)
+    r, c, tile = best.split("|")
     if use_cache:
-        cache[key] = {"ratio": float(r), "collapsed": bool(int(c)), "ms": times}
+        cache[key] = {"ratio": float(r), "collapsed": bool(int(c)), "tile": int(tile), "ms": times}
         store_cache(cache)
-    return float(r), bool(int(c)), times
+    return float(r), bool(int(c)), int(tile), times

@@ -21,13 +21,14 @@ def offsets(sizes):
     return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
 
 
-def check_batched(rtf, orc, ws, cells, sample_counts, seed):
+def check_batched(rtf, orc, ws, cells, sample_counts, seed, tile=0):
     rng = np.random.default_rng(seed)
     w = np.concatenate(ws)
     eo = offsets([a.size for a in ws])
     co = offsets(cells)
-    f = rtf.build_batched(to_dev(w), to_dev(eo), to_dev(co))
+    f = rtf.build_batched(to_dev(w), to_dev(eo), to_dev(co), tile=tile)
     f.check()
+    assert f.desc.tile == (tile or 2048)
     ref = orc.forest(w, elem_off=eo, cell_off=co)
     assert_forest(f, ref, f"D={len(ws)}")
     so = offsets(sample_counts)
@@ -45,8 +46,13 @@ def check_batched(rtf, orc, ws, cells, sample_counts, seed):
     return f
 
 
-def test_batched_random_sizes(rtf, orc):
-    note("batched D=60 random sizes")
+# the build tiles the tuner chooses from (0: the default, 2048 elements)
+TILES = [0, 1024]
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_batched_random_sizes(rtf, orc, tile):
+    note(f"batched D=60 random sizes tile={tile}")
     rng = np.random.default_rng(21)
     sizes = rng.integers(1, 6000, 60)
     sizes[:5] = [1, 1, 2, 4096, 4097]
@@ -60,19 +66,21 @@ def test_batched_random_sizes(rtf, orc):
     counts = rng.integers(0, 3000, 60)
     counts[3] = 0
     counts[10:13] = 0
-    check_batched(rtf, orc, ws, cells, counts, 1)
+    check_batched(rtf, orc, ws, cells, counts, 1, tile)
 
 
-def test_batched_tile_straddling(rtf, orc):
-    """Distributions that start and end at and around the 4096-element tiles."""
-    note("batched straddling tiles")
+@pytest.mark.parametrize("tile", TILES)
+def test_batched_tile_straddling(rtf, orc, tile):
+    """Distributions that start and end at and around the edges of 1024- and
+    2048-element tiles."""
+    note(f"batched straddling tiles tile={tile}")
     rng = np.random.default_rng(22)
-    sizes = [4095, 1, 4096, 2, 8190, 1, 1, 1, 12289, 3, 4096, 4096]
+    sizes = [4095, 1, 4096, 2, 8190, 1, 1, 1, 12289, 3, 4096, 4096, 1023, 1, 1024, 2047, 1025]
     ws = [random_weights(rng, s, zero_frac=0.1) for s in sizes]
     cells = [s for s in sizes]
     cells[4] = 1
     cells[8] = 50000
-    check_batched(rtf, orc, ws, cells, [500] * len(sizes), 2)
+    check_batched(rtf, orc, ws, cells, [500] * len(sizes), 2, tile)
 
 
 def test_batched_zero_distribution(rtf, orc):
@@ -95,17 +103,18 @@ def test_batched_zero_distribution(rtf, orc):
         assert np.array_equal(idx[10 * d:10 * d + 10], i_ref)
 
 
-def test_batched_many_tiny(rtf, orc):
+@pytest.mark.parametrize("tile", TILES)
+def test_batched_many_tiny(rtf, orc, tile):
     """Thousands of tiny distributions with a few uniforms each, so that a
     chunk of the sampling kernel spans more distributions than it can stage
     and its lanes walk the offsets; some get no uniform at all."""
-    note("batched D=3000 tiny")
+    note(f"batched D=3000 tiny tile={tile}")
     rng = np.random.default_rng(25)
     sizes = rng.integers(1, 6, 3000)
     ws = [random_weights(rng, int(s)) for s in sizes]
     counts = rng.integers(0, 4, 3000)
     counts[1000:1100] = 300  # a stretch that chunks can stage
-    check_batched(rtf, orc, ws, [int(s) for s in sizes], counts, 4)
+    check_batched(rtf, orc, ws, [int(s) for s in sizes], counts, 4, tile)
 
 
 def test_batched_staged_cells(rtf, orc):
@@ -136,14 +145,14 @@ def test_batched_staged_cells(rtf, orc):
         assert_samples(idx[so[d]:so[d + 1]], x[so[d]:so[d + 1]], i_ref, x_ref)
 
 
-@pytest.mark.parametrize("ratio", [0.25, 1.0])
-def test_c4_batched_uneven_full(rtf, orc, ratio):
+@pytest.mark.parametrize("ratio,tile", [(0.25, 0), (1.0, 0), (0.125, 1024)])
+def test_c4_batched_uneven_full(rtf, orc, ratio, tile):
     """10,000 distributions, sizes log-uniform in [16, 65536], uniform or
     Pareto(1.2) weights, ceil(64 n_d / 1000) uniforms each; guide cells
-    m_d = ratio n_d (the benchmark runs 1/4)."""
+    m_d = ratio n_d and the build tile as the tuner may pick them."""
     import torch
     from paper_1901_05423_amd import workloads as wl
-    note(f"C4 batched D=10000 ratio={ratio}")
+    note(f"C4 batched D=10000 ratio={ratio} tile={tile}")
     r = wl.rng(wl.C4_BATCHED)
     v, eo, so = wl.batched_uneven(r)
     u = wl.uniforms(r, int(so[-1]))
@@ -154,7 +163,7 @@ def test_c4_batched_uneven_full(rtf, orc, ratio):
     note(f"C4 n_total={eo[-1]} S={so[-1]}: building")
     eod = to_dev(eo)
     cod = rtf.cells_like(eod, ratio)
-    f = rtf.build_batched(q, eod, cod)
+    f = rtf.build_batched(q, eod, cod, tile=tile)
     f.check()
     ref = orc.forest(q_ref, elem_off=eo, cell_off=cod.cpu().numpy())
     note("C4 oracle forest done")
@@ -179,7 +188,7 @@ def quantised_map(orc, img, marginal):
     return v, q, eo
 
 
-def check_2d(rtf, orc, img, marginal, pairs, seed, zero_rows=False, ratio=1.0):
+def check_2d(rtf, orc, img, marginal, pairs, seed, zero_rows=False, ratio=1.0, tile=0):
     rng = np.random.default_rng(seed)
     R, C = img.shape
     v, q_ref, eo = quantised_map(orc, img, marginal)
@@ -187,7 +196,7 @@ def check_2d(rtf, orc, img, marginal, pairs, seed, zero_rows=False, ratio=1.0):
     assert np.array_equal(q.cpu().numpy(), q_ref)
     eod = to_dev(eo)
     cod = rtf.cells_like(eod, ratio)
-    f = rtf.build_batched(q, eod, cod)
+    f = rtf.build_batched(q, eod, cod, tile=tile)
     if zero_rows:  # an all-zero row is a distribution without mass
         import paper_1901_05423_amd as rtfm
         with pytest.raises(rtfm.RtfError):
@@ -232,15 +241,15 @@ def test_2d_two_pairs_per_lane(rtf, orc):
     check_2d(rtf, orc, img, marg, 9_000_001, 5)
 
 
-@pytest.mark.parametrize("ratio", [0.25, 1.0])
-def test_c3_2d_full_map(rtf, orc, ratio):
+@pytest.mark.parametrize("ratio,tile", [(0.25, 0), (1.0, 0), (0.25, 1024)])
+def test_c3_2d_full_map(rtf, orc, ratio, tile):
     """4096 x 4096 log-normal(0, 1.5) map with 8 hot spots: forest of the
-    marginal plus 4096 rows bit-exact at m_d = ratio n_d (the benchmark runs
-    1/4), 2^20 pairs checked."""
+    marginal plus 4096 rows bit-exact at m_d = ratio n_d with the build tile
+    the tuner may pick, 2^20 pairs checked."""
     from paper_1901_05423_amd import workloads as wl
-    note(f"C3 2D 4096x4096 ratio={ratio}")
+    note(f"C3 2D 4096x4096 ratio={ratio} tile={tile}")
     img, marg = wl.map_2d(wl.rng(wl.C3_MAP_2D))
-    f, q_ref, eo, co = check_2d(rtf, orc, img, marg, 1 << 20, 4, ratio=ratio)
+    f, q_ref, eo, co = check_2d(rtf, orc, img, marg, 1 << 20, 4, ratio=ratio, tile=tile)
     note("C3 samples match; comparing forest")
     assert_forest(f, orc.forest(q_ref, elem_off=eo, cell_off=co), "C3")
 

@@ -19,10 +19,11 @@ def rtf():
     return rtf
 
 
-def build_and_compare(rtf, orc, w, m, S_extra=20000, seed=0, baselines=True):
+def build_and_compare(rtf, orc, w, m, S_extra=20000, seed=0, baselines=True, tile=0):
     rng = np.random.default_rng(seed)
-    f = rtf.build(to_dev(w), m)
+    f = rtf.build(to_dev(w), m, tile=tile)
     f.check()
+    assert f.desc.tile == (tile or 2048)
     ref = orc.forest(w, m=m)
     assert_forest(f, ref, f"n={w.size} m={m}")
     u = critical_u(ref.key, int(ref.W[0]), m, extra=S_extra, rng=rng)
@@ -218,12 +219,15 @@ def test_c2_zipf_2e20_full_forest(rtf, orc):
 # The benchmark sizes the guide table with the autotuner, which picks among
 # these ratios m/n (paper_1901_05423_amd/tune.py); every candidate is checked
 # at full size for the uniform workload, the usual picks for the Zipf one.
-H24_CASES = [("uniform", r) for r in (0.25, 0.125, 0.5, 1.0, 2.0)] + \
-            [("zipf", r) for r in (0.25, 0.125, 1.0)]
+# The tuner also picks the build tile; both tiles are checked at the usual
+# ratio.
+H24_CASES = [("uniform", r, 0) for r in (0.25, 0.125, 0.5, 1.0, 2.0)] + \
+            [("zipf", r, 0) for r in (0.25, 0.125, 1.0)] + \
+            [("uniform", 0.25, 1024), ("zipf", 0.25, 1024)]
 
 
-@pytest.mark.parametrize("kind,ratio", H24_CASES)
-def test_h24_full_size(rtf, orc, kind, ratio):
+@pytest.mark.parametrize("kind,ratio,tile", H24_CASES)
+def test_h24_full_size(rtf, orc, kind, ratio, tile):
     """The benchmark's workload and launch configuration: n = 2^24, m = ratio n,
     all S = 2^26 uniforms sampled in one call as the benchmark does.  Forest,
     guide table and cell records bit-exact against the oracle's; every 16th
@@ -232,7 +236,7 @@ def test_h24_full_size(rtf, orc, kind, ratio):
     from paper_1901_05423_amd import workloads as wl
     n = 1 << 24
     m = max(1, int(round(ratio * n)))
-    note(f"H24 {kind} n=2^24 m={m} S=2^26")
+    note(f"H24 {kind} n=2^24 m={m} tile={tile} S=2^26")
     r = wl.rng(wl.H24_UNIFORM if kind == "uniform" else wl.H24_ZIPF)
     v = wl.weights_uniform(r, n) if kind == "uniform" else wl.weights_zipf(r, n)
     u = wl.uniforms(r, 1 << 26)
@@ -240,7 +244,7 @@ def test_h24_full_size(rtf, orc, kind, ratio):
     q, _ = rtf.quantize(to_dev(v))
     assert np.array_equal(q.cpu().numpy(), q_ref)
     note("H24 quantised weights match; building")
-    f = rtf.build(q, m)
+    f = rtf.build(q, m, tile=tile)
     f.check()
     ref = orc.forest(q_ref, m=m)
     note("H24 oracle forest done; comparing")
@@ -362,3 +366,37 @@ def test_adversarial_weights(rtf, orc, kind, seed):
     note(f"adversarial {kind} seed={seed} n={n} m={m}")
     w = adversarial(kind, n, rng)
     build_and_compare(rtf, orc, w, m, S_extra=5000, seed=seed, baselines=seed == 0)
+
+
+@pytest.mark.parametrize("case", CASES[::2], ids=lambda c: "n%d_m%d" % (c[0], c[1]))
+def test_tile_1024(rtf, orc, case):
+    """The same forests built in 1024-element tiles of 256 threads (the
+    other tile the tuner may pick): bit for bit the oracle's."""
+    n, m, zf, skew, trail = case
+    note(f"tile 1024 n={n} m={m} zeros={zf} skew={skew} trailing={trail}")
+    rng = np.random.default_rng(n * 7919 + m)
+    w = random_weights(rng, n, zero_frac=zf, skew=skew)
+    if trail:
+        w[-trail:] = 0
+        if w.sum() == 0:
+            w[0] = 5
+    build_and_compare(rtf, orc, w, m, seed=n + m, baselines=False, tile=1024)
+
+
+def test_tile_1024_deferrals(rtf, orc):
+    """Tiles of 1024 with long zero runs and one heavy tree: deferred nodes
+    near every tile edge and tiles that defer more than they can list."""
+    note("tile 1024 zero runs and one tree")
+    rng = np.random.default_rng(77)
+    w = random_weights(rng, 50000)
+    w[:3000] = 0
+    w[10000:14000] = 0
+    w[-5000:] = 0
+    for m in (1, 2, 1000, 50000):
+        build_and_compare(rtf, orc, w, m, seed=m, baselines=False, tile=1024)
+
+
+def test_tile_rejected(rtf):
+    import paper_1901_05423_amd as rtfm
+    with pytest.raises(rtfm.RtfError):
+        rtf.build(to_dev(np.ones(100, np.uint32)), 100, tile=512)
