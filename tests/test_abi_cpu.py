@@ -75,6 +75,16 @@ def test_argument_errors_before_launch(L):
     assert r == rtf.RTF_ERR_SIZE
     r = L.rtf_build(fake, 1000, 1000, fake, 64, None, ctypes.byref(desc))
     assert r == rtf.RTF_ERR_WORKSPACE
+    # build tiles: 1024 or 2048 elements, anything else refused on the host
+    for tile in (0, 512, 1000, 4096, -2048):
+        r = L.rtf_build_tiled(fake, 1000, 1000, tile, fake, 1 << 30, None, ctypes.byref(desc))
+        assert r == rtf.RTF_ERR_INVALID_ARG, tile
+        r = L.rtf_build_batched_tiled(fake, fake, fake, 2, 1000, 1000, tile, fake, 1 << 30, None,
+                                      ctypes.byref(desc))
+        assert r == rtf.RTF_ERR_INVALID_ARG, tile
+    for tile in (1024, 2048):  # a valid tile still meets the workspace check
+        r = L.rtf_build_tiled(fake, 1000, 1000, tile, fake, 64, None, ctypes.byref(desc))
+        assert r == rtf.RTF_ERR_WORKSPACE
     r = L.rtf_sample(None, fake, 10, fake, None, None)
     assert r == rtf.RTF_ERR_INVALID_ARG
     r = L.rtf_sample(ctypes.byref(desc), fake, 10, fake, None, None)  # empty descriptor
