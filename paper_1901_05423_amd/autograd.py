@@ -9,7 +9,8 @@ from __future__ import annotations
 
 import torch
 
-from . import backward, build_batched, cells_like, quantize, sample_batched
+from . import (RTF_ERR_VALUE, RtfError, backward, build_batched, cells_like, quantize,
+               sample_batched)
 
 
 class RTFSample(torch.autograd.Function):
@@ -24,6 +25,12 @@ class RTFSample(torch.autograd.Function):
                 nothing read back, so forward and backward can be captured
                 in a HIP graph; x is then a view of the plan's buffer
     Returns x float64[S].
+
+    Without a plan the forward raises RtfError on a negative, NaN or
+    infinite weight (RTF_ERR_VALUE) and on a distribution whose weights are
+    all zero (RTF_ERR_ZERO_TOTAL); it synchronises for that, as it does to
+    size the workspace.  With a plan nothing is read back: call
+    plan.check() to raise on the same errors.
     """
 
     @staticmethod
@@ -35,8 +42,12 @@ class RTFSample(torch.autograd.Function):
             ctx.plan = plan
             ctx.save_for_backward(u)
             return x.view(-1)
-        q, scale = quantize(v.detach().contiguous(), elem_off)
+        status = torch.zeros(1, dtype=torch.int32, device=v.device)
+        q, scale = quantize(v.detach().contiguous(), elem_off, status=status)
         f = build_batched(q, elem_off, cells_like(elem_off, cell_ratio))
+        if int(status.item()) & (1 << RTF_ERR_VALUE):
+            raise RtfError(RTF_ERR_VALUE, "rtf_quantize_f32")
+        f.check()
         idx, x = sample_batched(f, sample_off, u, want_x=True)
         ctx.plan = None
         ctx.forest = f

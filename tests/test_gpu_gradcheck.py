@@ -105,3 +105,28 @@ def test_fd_recomputed_indices(rtf, orc):
     err = np.abs(fd - g)
     assert err.max() <= 1e-3 * np.abs(g).max(), (err.max(), np.abs(g).max())
     assert np.linalg.norm(fd - g) <= 1e-3 * np.linalg.norm(g)
+
+
+def test_rtfsample_rejects_bad_weights(rtf):
+    """The differentiable forward raises on a NaN or negative weight and on a
+    distribution whose weights are all zero, instead of sampling them."""
+    import torch
+    note("RTFSample data errors")
+    dev = torch.device("cuda:0")
+    eo = torch.tensor([0, 5, 10], dtype=torch.int64, device=dev)
+    so = torch.tensor([0, 4, 8], dtype=torch.int64, device=dev)
+    u = torch.arange(8, dtype=torch.int64, device=dev) * (1 << 60)
+    good = torch.rand(10, device=dev) + 0.1
+    x = rtf.RTFSample.apply(good, u, eo, so, 1.0)
+    assert x.shape == (8,) and bool(torch.isfinite(x).all())
+    for bad_value, code in ((float("nan"), rtf.RTF_ERR_VALUE), (-1.0, rtf.RTF_ERR_VALUE)):
+        v = good.clone()
+        v[3] = bad_value
+        with pytest.raises(rtf.RtfError) as e:
+            rtf.RTFSample.apply(v, u, eo, so, 1.0)
+        assert e.value.code == code
+    v = good.clone()
+    v[5:] = 0.0
+    with pytest.raises(rtf.RtfError) as e:
+        rtf.RTFSample.apply(v, u, eo, so, 1.0)
+    assert e.value.code == rtf.RTF_ERR_ZERO_TOTAL
