@@ -404,3 +404,54 @@ def test_c5_grad_full(rtf, orc):
     L = sum sin(7x): dL/dlogits of 4 distributions checked against the oracle."""
     note("C5 grad D=256 n=4096 2^20 each")
     check_grad(rtf, orc, 256, 4096, 1 << 20, [0, 1, 128, 255], 5, ratio=0.25)
+
+
+@pytest.fixture(scope="module")
+def million_tiny(orc):
+    """2^20 distributions of 1 to 8 float32 weights (one in ten zero, every
+    distribution with mass), their oracle quantisation and guide offsets."""
+    rng = np.random.default_rng(31)
+    D = 1 << 20
+    sizes = rng.integers(1, 9, D)
+    eo = offsets(sizes)
+    n = int(eo[-1])
+    v = (1.0 - rng.random(n)).astype(np.float32)
+    v[rng.random(n) < 0.1] = 0.0
+    v[eo[:-1][np.add.reduceat(v, eo[:-1]) == 0]] = 0.5
+    q_ref, s_ref = orc.quantize(v, eo)
+    co = offsets(np.maximum(1, sizes // 2))
+    return v, eo, co, q_ref, s_ref, rng
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_batched_million_tiny(rtf, orc, million_tiny, tile):
+    """2^20 distributions of 1 to 8 weights each (4.7M weights): far more
+    distributions than one block of any kernel holds, so the quantisation's
+    blocks span hundreds of distributions each (global atomics), the
+    parameters go through k_dist_finish, tiles hold hundreds of distribution
+    starts, and sampling chunks walk the offsets.  Quantised weights, totals,
+    forest and cell records bit-exact; the samples of 3000 distributions
+    (the first, the last, and random ones) checked one by one."""
+    import torch
+    v, eo, co, q_ref, s_ref, rng0 = million_tiny
+    note(f"batched D=2^20 tiny tile={tile}")
+    rng = np.random.default_rng(32 + tile)
+    D = eo.size - 1
+    eod = to_dev(eo)
+    q, s = rtf.quantize(to_dev(v), eod)
+    assert np.array_equal(q.cpu().numpy(), q_ref)
+    assert np.array_equal(s.cpu().numpy(), s_ref)
+    f = rtf.build_batched(q, eod, to_dev(co), tile=tile)
+    f.check()
+    assert_forest(f, orc.forest(q_ref, elem_off=eo, cell_off=co), "D=2^20")
+    counts = rng.integers(0, 4, D)
+    so = offsets(counts)
+    u = rng.integers(0, 2 ** 64, int(so[-1]), dtype=np.uint64)
+    idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
+    idx, x = idx.cpu().numpy(), x.cpu().numpy()
+    for d in np.unique(np.concatenate([[0, D - 1], rng.integers(0, D, 3000)])):
+        a, b = so[d], so[d + 1]
+        if a < b:
+            i_ref, x_ref = orc.search(q_ref[eo[d]:eo[d + 1]], u[a:b])
+            assert_samples(idx[a:b], x[a:b], i_ref, x_ref)
+    torch.cuda.synchronize()
