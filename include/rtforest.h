@@ -239,7 +239,10 @@ rtf_status rtf_sample(const rtf_forest *f, const uint64_t *u, int64_t S,
 /*
  * Alg. 2 for a batch: samples [sample_off[d], sample_off[d+1]) of u belong to
  * distribution d (int64[D+1] device offsets, non-decreasing, sample_off[D] = S;
- * empty ranges allowed).  Indices are local to each distribution.
+ * empty ranges allowed).  Indices are local to each distribution.  Offsets
+ * that break those rules (they are not read back to the host) give
+ * unspecified indices, but every sample is still written once, the kernels
+ * stay within the forest, u and the outputs, and they finish.
  */
 rtf_status rtf_sample_batched(const rtf_forest *f, const int64_t *sample_off,
                               const uint64_t *u, int64_t S, int32_t *out_idx,
@@ -282,6 +285,9 @@ rtf_status rtf_sample_cutpoint_bsearch(const rtf_forest *f, const uint64_t *u,
  *   out       uint32[n_total]; scale double[D]
  *   status    uint32 device status word that receives RTF_ERR_VALUE for a
  *             negative, NaN or infinite weight (may be NULL)
+ * Offsets that break those rules (they are not read back to the host) give
+ * unspecified q and scale, but the kernels stay within v, out, scale and
+ * elem_off and finish.
  */
 rtf_status rtf_quantize_f32(const float *v, const int64_t *elem_off, int32_t D,
                             int64_t n_total, uint32_t *out, double *scale,

@@ -121,7 +121,9 @@ __global__ __launch_bounds__(QT) void k_qmax(const float *__restrict__ v,
         const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
         if (i >= b1) break;
         if (!one) {
-            while (i >= dend) {
+            // d stays within [dfirst, dlast] even for offsets that break the
+            // rules, so the LDS slots and the maxima stay in bounds
+            while (i >= dend && d < dlast) {
                 if (mx) {
                     if (lds) atomicMax(s_dmax + (d - dfirst), mx);
                     else atomicMax(max_word(scale, d), mx);
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(QT) void k_qapply(const float *__restrict__ v,
         const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
         if (i >= b1) break;
         if (i >= dend) {
-            while (i >= dend) {
+            while (i >= dend && d + 1 < D) {  // d < D for any offsets
                 ++d;
                 dend = off[d + 1];
             }

@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
         // otherwise each lane walks the offsets in global memory.
         const int64_t ok = sample_off[d + (int32_t)threadIdx.x <= D ? d + (int32_t)threadIdx.x : D];
         s_soff[threadIdx.x] = ok;
-        const int nb = __syncthreads_count(threadIdx.x > 0 && d + (int32_t)threadIdx.x <= D && ok < cend);
+        const int nb = __syncthreads_count(threadIdx.x > 0 && d + (int32_t)threadIdx.x < D && ok < cend);
         if (nb < CHUNK_DISTS - 1) {  // offsets d .. d + nb + 1 held, the last at or past cend
             const uint4 *src = reinterpret_cast<const uint4 *>(dists + d);
             for (int q = threadIdx.x; q < 4 * (nb + 1); q += 256) s_dist[q] = src[q];
@@ -347,11 +347,12 @@ __global__ __launch_bounds__(256) void k_sample(const Node *__restrict__ nodes,
         for (int k = 0; k < SCHUNK / 256; k += 2) {
             const int64_t sa = c0 + threadIdx.x + 256 * k, sb = sa + 256;
             if (sa >= S) break;
-            while (sa >= dend) dend = sample_off[++d + 1];
+            // (d stays below D even for offsets that break the rules)
+            while (sa >= dend && d + 1 < D) dend = sample_off[++d + 1];
             const int32_t da = d;
             const bool has_b = sb < S;
             if (has_b)
-                while (sb >= dend) dend = sample_off[++d + 1];
+                while (sb >= dend && d + 1 < D) dend = sample_off[++d + 1];
             two(sa, sb, has_b, dists[da], dists[d]);
         }
         __syncthreads();  // s_soff is rewritten by the next chunk
@@ -390,7 +391,9 @@ __global__ __launch_bounds__(SB_T) __attribute__((amdgpu_waves_per_eu(8))) void 
     for (int64_t s0 = r0; s0 < r1;) {  // uniform loop over the share's segments
         const int32_t d = __builtin_amdgcn_readfirstlane(block_find_segment<SB_T>(sample_off, D, s0));
         const int64_t de = sample_off[d + 1];
-        const int64_t e = de < r1 ? de : r1;
+        // the segment ends past s0 (offsets that break the rules still make
+        // progress, one sample at a time)
+        const int64_t e = de > s0 ? (de < r1 ? de : r1) : s0 + 1;
         const Dist P = dists[d];
         const bool zero = P.flags & DIST_ZERO;
         const bool staged = !zero && P.m <= LCELLS && e - s0 >= STAGE_MIN * P.m;

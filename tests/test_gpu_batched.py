@@ -455,3 +455,43 @@ def test_batched_million_tiny(rtf, orc, million_tiny, tile):
             i_ref, x_ref = orc.search(q_ref[eo[d]:eo[d + 1]], u[a:b])
             assert_samples(idx[a:b], x[a:b], i_ref, x_ref)
     torch.cuda.synchronize()
+
+
+def test_batched_offsets_out_of_rule(rtf, orc):
+    """Sample offsets that break the rules (decreasing, not ending at S) give
+    unspecified indices but bounded work: the call returns, every sample gets
+    an index of some distribution (or -1) and an x in [0, 1]; both sampling
+    kernels (LDS-staged cells and chunks) and the batched quantisation are
+    run this way.  Valid offsets afterwards still give the oracle's answers."""
+    import torch
+    note("batched offsets out of rule")
+    rng = np.random.default_rng(41)
+    sizes = [3000, 50, 4096, 7, 1000]
+    ws = [random_weights(rng, s) for s in sizes]
+    w = np.concatenate(ws)
+    eo, co = offsets(sizes), offsets([700, 10, 1024, 2, 250])
+    f = rtf.build_batched(to_dev(w), to_dev(eo), to_dev(co))
+    f.check()
+    nmax = max(sizes)
+    for S in (200000, 3000):  # many samples per cell (staged cells), few (chunks)
+        u = rng.integers(0, 2 ** 64, S, dtype=np.uint64)
+        for so in (np.array([0, S, S // 2, S // 3, 5, 1], np.int64),
+                   np.array([0, 10, 20, 30, 40, 50], np.int64),
+                   np.array([S, 0, S, 0, S, 0], np.int64)):
+            idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
+            torch.cuda.synchronize()
+            idx, x = idx.cpu().numpy(), x.cpu().numpy()
+            assert ((idx >= -1) & (idx < nmax)).all()
+            ok = idx >= 0
+            assert ((x[ok] >= 0) & (x[ok] <= 1)).all()
+        so = offsets([S // 5] * 4 + [S - 4 * (S // 5)])
+        idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
+        idx, x = idx.cpu().numpy(), x.cpu().numpy()
+        for d in range(5):
+            i_ref, x_ref = orc.search(ws[d], u[so[d]:so[d + 1]])
+            assert_samples(idx[so[d]:so[d + 1]], x[so[d]:so[d + 1]], i_ref, x_ref)
+    v = (1.0 - rng.random(w.size)).astype(np.float32)
+    for bad in (np.array([0, 9000, 100, 5000, 2, 1], np.int64), np.array([0, 1, 2, 3, 4, 5], np.int64)):
+        q, s = rtf.quantize(to_dev(v), to_dev(bad))
+        torch.cuda.synchronize()
+        assert q.numel() == v.size and s.numel() == 5
