@@ -1,8 +1,8 @@
 """Autotuner for the guide-table size, the build tile and the descent form.
 
 The sampled indices do not depend on the number of guide cells m, nor on the
-build tile; only speed does.  The paper leaves m open ("as much memory as
-affordable, or proportional to n", Sec. 3).  More cells let more samples
+build tile; only speed does.  The paper leaves m to the user: whatever
+memory can be spared, or a size that grows with n (Sec. 3).  More cells let more samples
 finish in one cell record, but a larger table costs build bytes and cache
 capacity.  Batches of many small distributions build faster in 1024-element
 tiles, one large distribution in 2048-element ones.  `best_cell_ratio` and
