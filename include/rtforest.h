@@ -142,8 +142,10 @@ rtf_status rtf_build(const uint32_t *w, int64_t n, int64_t m, void *ws,
  *             strictly increasing, cell_off[D] = m_total
  * Node and leaf references are global (leaf i of distribution d is
  * elem_off[d] + i); the sampling calls return indices local to d.  Offsets
- * are copied into the workspace.  Offsets that break the rules above are
- * undefined behaviour (they are not read back to the host).
+ * are copied into the workspace.  They are not read back to the host, so
+ * offsets that break the rules above are found on the device: rtf_check then
+ * reports RTF_ERR_INVALID_ARG, the forest's contents are unspecified, and
+ * the build and every later call on the forest stay within its workspace.
  */
 rtf_status rtf_build_batched(const uint32_t *w, const int64_t *elem_off,
                              const int64_t *cell_off, int32_t D,

@@ -266,6 +266,10 @@ __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t 
 // Each block sums TS_TILES tiles whose loads are all issued before the first
 // reduction, so that enough bytes are in flight to stream at HBM rate.
 
+// A distribution index from a search over the caller's offsets, kept in
+// [0, D) also for offsets that break the rules.
+__device__ inline int32_t clamp_dist(int32_t d, int32_t D) { return d < 0 ? 0 : (d < D ? d : D - 1); }
+
 __device__ inline uint64_t wave_sum(uint64_t x) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -320,12 +324,12 @@ __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *
                 const int32_t d = wave_upper_bound(a.src_elem_off, a.D, t * TILE - 1);  // first off >= t*TILE
                 if (lane == 0) s_first[k] = d;
             } else {
-                const int32_t d = wave_upper_bound(a.src_elem_off, a.D, t * TILE) - 1;
+                const int32_t d = clamp_dist(wave_upper_bound(a.src_elem_off, a.D, t * TILE) - 1, a.D);
                 if (lane == 0) a.tile_dist[t] = d;
             }
         }
         if (w == 0 && t0 + TS_TILES >= a.ntiles) {
-            const int32_t d = wave_upper_bound(a.src_elem_off, a.D, a.n_total - 1) - 1;
+            const int32_t d = clamp_dist(wave_upper_bound(a.src_elem_off, a.D, a.n_total - 1) - 1, a.D);
             if (lane == 0) {
                 a.tile_dist[a.ntiles] = d;
                 a.tile_dist[a.ntiles + 1] = d;
@@ -347,6 +351,7 @@ __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *
         for (int32_t d = dlo + tid; d < a.D; d += BT) {
             int64_t e = a.src_elem_off[d];
             if (e >= end) break;
+            if (e < base || e >= a.n_total) continue;  // only offsets that break the rules
             int64_t off = e - base;
             int64_t tq = off / ITEMS;
             uint64_t L = s_thr[tq];
@@ -366,15 +371,31 @@ __global__ __launch_bounds__(T::BT) void k_tile_sums(BuildArgs a, bool vec) {
     const int tid = threadIdx.x;
     const int64_t t0 = (int64_t)blockIdx.x * TS_TILES;
     if (blockIdx.x == 0) {
-        // this build's status word, run list and the offsets later kernels read
+        // this build's status word, run list and the offsets later kernels
+        // read.  The caller's offsets are checked first: offsets that break
+        // the rules (0 first, strictly increasing, n_total and m_total last)
+        // are reported as RTF_ERR_INVALID_ARG and replaced in the workspace by
+        // a valid partition (one weight and one cell for each distribution
+        // but the last), so that every later kernel stays in bounds.
+        bool bad = false;
+        if (BATCHED) {
+            for (int64_t q = tid; q <= a.D; q += BT) {
+                const int64_t e = a.src_elem_off[q], c = a.src_cell_off[q];
+                if (q == 0) bad = bad || e != 0 || c != 0;
+                else bad = bad || e <= a.src_elem_off[q - 1] || c <= a.src_cell_off[q - 1];
+                if (q == a.D) bad = bad || e != a.n_total || c != a.m_total;
+            }
+        }
+        bad = __syncthreads_or(bad);
         if (tid == 0) {
-            *a.status = 0u;
+            *a.status = bad ? status_bit(RTF_ERR_INVALID_ARG) : 0u;
             *a.run_count = 0;
             *a.item_count = 0u;
         }
         for (int64_t q = tid; q <= a.D; q += BT) {
-            a.elem_off[q] = BATCHED ? a.src_elem_off[q] : (q ? a.n_total : 0);
-            a.cell_off[q] = BATCHED ? a.src_cell_off[q] : (q ? a.m_total : 0);
+            const bool own = BATCHED && !bad;
+            a.elem_off[q] = own ? a.src_elem_off[q] : (q == a.D ? a.n_total : (BATCHED ? q : 0));
+            a.cell_off[q] = own ? a.src_cell_off[q] : (q == a.D ? a.m_total : (BATCHED ? q : 0));
         }
     }
     if (vec && (t0 + TS_TILES) * TILE <= a.n_total)

@@ -1,5 +1,7 @@
 """GPU parity for many distributions at once (Sec. 5): batched builds and
 samples, the two-dimensional inversion, and the adjoint of x."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -495,3 +497,44 @@ def test_batched_offsets_out_of_rule(rtf, orc):
         q, s = rtf.quantize(to_dev(v), to_dev(bad))
         torch.cuda.synchronize()
         assert q.numel() == v.size and s.numel() == 5
+
+
+def test_build_offsets_out_of_rule(rtf, orc):
+    """Build offsets that break the rules (not increasing, not starting at 0,
+    not ending at the totals) are reported by rtf_check as
+    RTF_ERR_INVALID_ARG; the build and sampling on its forest stay in bounds
+    and return.  The same workspace then builds valid offsets correctly."""
+    import torch
+    import paper_1901_05423_amd as rtfm
+    note("build offsets out of rule")
+    rng = np.random.default_rng(43)
+    sizes = [500, 300, 900, 1200]
+    ws = [random_weights(rng, s) for s in sizes]
+    w = np.concatenate(ws)
+    n, D = w.size, len(sizes)
+    eo_ok, co_ok = offsets(sizes), offsets([100, 100, 100, 100])
+    bad_cases = [
+        (np.array([0, 500, 300, 1800, n], np.int64), co_ok),   # not increasing
+        (eo_ok, np.array([0, 100, 100, 300, 400], np.int64)),  # repeated cell offset
+        (np.array([7, 500, 800, 1700, n], np.int64), co_ok),   # not starting at 0
+        (np.array([0, 500, 800, 1700, n - 1], np.int64), co_ok),  # not ending at n_total
+    ]
+    wd = to_dev(w)
+    so = offsets([1000] * D)
+    u = rng.integers(0, 2 ** 64, int(so[-1]), dtype=np.uint64)
+    for eo, co in bad_cases:
+        nb = rtf.lib().rtf_workspace_bytes_batched(D, n, int(co_ok[-1]))
+        wsp = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        desc = rtfm.rtf_forest()
+        eod, cod = to_dev(eo), to_dev(co)
+        rtfm._check(rtf.lib().rtf_build_batched(rtfm._ptr(wd), rtfm._ptr(eod), rtfm._ptr(cod), D, n,
+                                                int(co_ok[-1]), rtfm._ptr(wsp), nb, rtfm._stream(),
+                                                ctypes.byref(desc)), "rtf_build_batched")
+        f = rtfm.Forest(wsp, desc, wd.device)
+        with pytest.raises(rtfm.RtfError) as e:
+            f.check()
+        assert e.value.code == rtf.RTF_ERR_INVALID_ARG
+        idx, x = rtf.sample_batched(f, to_dev(so), to_dev(u))
+        torch.cuda.synchronize()
+        assert (idx.cpu().numpy() >= -1).all()
+    check_batched(rtf, orc, ws, [100] * D, [1000] * D, 5)
