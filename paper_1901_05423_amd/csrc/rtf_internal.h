@@ -10,7 +10,8 @@ namespace rtf {
 
 // A level above every real one (0..64): a boundary merges never cross, used
 // for cell changes, distribution changes, both array ends and the end of the
-// weights that carry mass (Alg. 1 sets the neighbour "to the maximum").
+// weights that carry mass (Alg. 1 gives the missing neighbours past the array
+// ends the largest distance).
 constexpr int SENT = 65;
 
 // Build tile shapes: BT threads x ITEMS consecutive elements per block.  The
