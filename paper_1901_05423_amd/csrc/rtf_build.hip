@@ -263,8 +263,9 @@ __device__ inline void store_node(Node *nodes, int64_t j, uint64_t key, int32_t 
 // k_tile_sums: the prefix-sum pass over the weights (Sec. 2.6 notes that the
 // prefix sum of an inversion method computes efficiently in parallel)
 // ---------------------------------------------------------------------------
-// Each block sums TS_TILES tiles whose loads are all issued before the first
-// reduction, so that enough bytes are in flight to stream at HBM rate.
+// Each block sums TS_TILES (one distribution: TS_SINGLE) tiles whose loads are
+// all issued before the first reduction, so that enough bytes are in flight
+// to stream at HBM rate.
 
 // A distribution index from a search over the caller's offsets, kept in
 // [0, D) also for offsets that break the rules.
@@ -279,7 +280,8 @@ __device__ inline uint64_t wave_sum(uint64_t x) {
 template <class T, bool BATCHED, bool FULL>
 __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *s_wave,
                                       uint64_t *s_thr, int32_t *s_first) {
-    constexpr int BT = T::BT, ITEMS = T::ITEMS, TILE = T::TILE, TS_TILES = T::TS_TILES;
+    constexpr int BT = T::BT, ITEMS = T::ITEMS, TILE = T::TILE;
+    constexpr int TS_TILES = BATCHED ? T::TS_TILES : T::TS_SINGLE;
     constexpr int NW = BT / 64;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     uint32_t r[TS_TILES][ITEMS];
@@ -315,7 +317,7 @@ __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *
     // first element (waves 0..TS_TILES-1), and the distribution holding that
     // element (waves TS_TILES..2 TS_TILES-1, into tile_dist); the block of the
     // last tile also fills tile_dist[ntiles] and tile_dist[ntiles + 1]
-    static_assert(2 * TS_TILES == BT / 64, "one wave per search");
+    static_assert(!BATCHED || 2 * TS_TILES == BT / 64, "one wave per search");
     {
         const int k = w % TS_TILES;
         const int64_t t = t0 + k;
@@ -364,7 +366,8 @@ __device__ inline void tile_sums_body(const BuildArgs &a, int64_t t0, uint64_t *
 
 template <class T, bool BATCHED>
 __global__ __launch_bounds__(T::BT) void k_tile_sums(BuildArgs a, bool vec) {
-    constexpr int BT = T::BT, TILE = T::TILE, TS_TILES = T::TS_TILES;
+    constexpr int BT = T::BT, TILE = T::TILE;
+    constexpr int TS_TILES = BATCHED ? T::TS_TILES : T::TS_SINGLE;
     __shared__ uint64_t s_wave[TS_TILES * (BT / 64)];
     __shared__ uint64_t s_thr[BT];
     __shared__ int32_t s_first[TS_TILES];
@@ -416,7 +419,8 @@ constexpr int PT = 1024;
 template <class T, bool BATCHED>
 __device__ inline void dist_params_of(const BuildArgs &a, int32_t d, uint64_t total) {
     constexpr int TILE = T::TILE;
-    const int64_t eo = a.elem_off[d], e1 = a.elem_off[d + 1];
+    // one distribution: the whole forest, known without a read
+    const int64_t eo = BATCHED ? a.elem_off[d] : 0, e1 = BATCHED ? a.elem_off[d + 1] : a.n_total;
     uint64_t G0 = 0, G1 = total;
     if (BATCHED) {
         G0 = a.tile_prefix[eo / TILE] + a.dist_local[d];
@@ -427,8 +431,8 @@ __device__ inline void dist_params_of(const BuildArgs &a, int32_t d, uint64_t to
     P.G0 = G0;
     P.eo = eo;
     P.n = e1 - eo;
-    P.co = a.cell_off[d];
-    P.m = a.cell_off[d + 1] - P.co;
+    P.co = BATCHED ? a.cell_off[d] : 0;
+    P.m = BATCHED ? a.cell_off[d + 1] - P.co : a.m_total;
     P.flags = 0;
     if (P.W == 0) {
         P.s = 0;
@@ -483,8 +487,10 @@ __global__ __launch_bounds__(PT) void k_dist_params(BuildArgs a) {
         if (threadIdx.x == 0) a.tile_prefix[nt] = total;
         return;
     }
-    __threadfence_block();
-    __syncthreads();
+    if (BATCHED) {  // the parameters read back this block's tile prefixes
+        __threadfence_block();
+        __syncthreads();
+    }
     if ((int32_t)threadIdx.x < a.D) dist_params_of<T, BATCHED>(a, (int32_t)threadIdx.x, total);
 }
 
@@ -1549,7 +1555,8 @@ void enqueue_build(const BuildArgs &a, hipStream_t st) {
     constexpr int BT = T::BT;
     const bool vec = (reinterpret_cast<uintptr_t>(a.w) & 15) == 0;
     const dim3 grid((unsigned)a.ntiles);
-    const dim3 sumgrid((unsigned)((a.ntiles + T::TS_TILES - 1) / T::TS_TILES));
+    const int ts = a.D > 1 ? T::TS_TILES : T::TS_SINGLE;
+    const dim3 sumgrid((unsigned)((a.ntiles + ts - 1) / ts));
     const dim3 fixgrid((unsigned)(a.ntiles < 1024 ? a.ntiles : 1024));
     if (a.D > 1) {
         hipLaunchKernelGGL((k_tile_sums<T, true>), sumgrid, dim3(BT), 0, st, a, vec);

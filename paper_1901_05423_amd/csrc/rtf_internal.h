@@ -35,8 +35,10 @@ struct Tiling {
     static constexpr int WIN = TILE + 128;
     // Deferred node records kept per tile; more make the fix-up redo the tile.
     static constexpr int DEFER_CAP = TILE / 16;
-    // Tiles summed per block of the tile-sum pass (one wave per search there).
+    // Tiles summed per block of the tile-sum pass: a batch's (one wave per
+    // search there), and one distribution's (only sums: more bytes per block).
     static constexpr int TS_TILES = BT / 128;
+    static constexpr int TS_SINGLE = BT / 64;
 };
 using Tile2048 = Tiling<512, 4, 8, 6>;  // 40 KB of LDS per tile: four per CU
 using Tile1024 = Tiling<256, 4, 7, 6>;  // 21 KB: seven per CU
@@ -167,21 +169,34 @@ __host__ __device__ inline int clz64(uint64_t x) { return x ? __builtin_clzll(x)
 
 // floor((2^128 - 1) / d) - 2^64 for a normalised d (top bit set): the
 // reciprocal of the 2-by-1 division of Moller and Granlund, "Improved
-// division by invariant integers" (IEEE Trans. Computers, 2011).  Computed by
-// restoring long division of (2^64 - 1 - d) * 2^64 + (2^64 - 1) by d.
+// division by invariant integers" (IEEE Trans. Computers, 2011).  An FP64
+// quotient 2^128 / d (a multiple of 2^12 in (2^64, 2^65], so its excess over
+// 2^64 converts exactly) is within 2^13 + 2 of it.  The exact remainder r of
+// (2^128 - 1) against (2^64 + v) d is then below 2^78 in magnitude; dividing
+// it by d once more in FP64 is off by at most one, and one comparison on
+// each side settles that.  A few dozen instructions instead of a 64-step
+// bit-serial division on the one thread that computes it per distribution.
 __host__ __device__ inline uint64_t reciprocal_2by1(uint64_t d) {
-    uint64_t hi = ~d, lo = ~0ull, q = 0;
-    for (int b = 0; b < 64; ++b) {
-        uint64_t top = hi >> 63;
-        hi = (hi << 1) | (lo >> 63);
-        lo <<= 1;
-        q <<= 1;
-        if (top || hi >= d) {
-            hi -= d;
-            q |= 1;
-        }
+    typedef unsigned __int128 u128;
+    typedef __int128 i128;
+    const double dd = (double)d;
+    const double z = 0x1p128 / dd - 0x1p64;  // exact subtraction, z in [0, 2^64]
+    uint64_t v = z >= 0x1p64 ? ~0ull : (uint64_t)z;
+    // r = (2^128 - 1) - (2^64 + v) d, computed modulo 2^128 (the complement)
+    i128 r = (i128)(~((((u128)1 << 64) | v) * d));
+    const double rd = (double)(int64_t)(r >> 64) * 0x1p64 + (double)(uint64_t)r;
+    const int64_t q = (int64_t)__builtin_floor(rd / dd);  // |q| <= 2^13 + 3
+    v += (uint64_t)q;
+    r -= (i128)q * (i128)d;
+    while (r < 0) {  // at most once
+        v -= 1;
+        r += d;
     }
-    return q;
+    while (r >= (i128)d) {  // at most once
+        v += 1;
+        r -= d;
+    }
+    return v;
 }
 
 // Key U = ceil(C * 2^64 / W) for 0 <= C < W, given s = clz(W), d = W << s
