@@ -119,6 +119,67 @@ def test_batched_many_tiny(rtf, orc, tile):
     check_batched(rtf, orc, ws, [int(s) for s in sizes], counts, 4, tile)
 
 
+def dist_records(f):
+    """The per-distribution parameter records as the build stored them, 64
+    bytes each: W, the reciprocal v, the global prefix G0, first element, n,
+    first cell, m, then the 32-bit normalisation shift and the flags."""
+    import torch
+    off = f.desc.dists - f.ws.data_ptr()
+    return f.ws[off:off + 64 * f.D].view(torch.int64).view(f.D, 8).cpu().numpy().view(np.uint64)
+
+
+def expected_params(w, eo, co):
+    """The same records from their definitions, in Python integers: W the sum
+    of the distribution's weights, s = clz64(W), v = floor((2^128 - 1) /
+    (W << s)) - 2^64 (the 2-by-1 reciprocal of Moller and Granlund), G0 the
+    sum of all weights before the distribution."""
+    rows, G = [], 0
+    for d in range(len(eo) - 1):
+        W = int(w[eo[d]:eo[d + 1]].astype(np.uint64).sum())
+        s = 64 - W.bit_length()
+        v = ((1 << 128) - 1) // (W << s) - (1 << 64)
+        rows.append([W, v, G, int(eo[d]), int(eo[d + 1] - eo[d]), int(co[d]),
+                     int(co[d + 1] - co[d]), s])
+        G += W
+    return rows
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("D", [1, 700, 2500])
+def test_dist_params_against_definition(rtf, D, tile):
+    """Each distribution's total, reciprocal, normalisation and global prefix,
+    bit for bit: one distribution of 2^20 weights (its own parameter path),
+    up to 1024 distributions (one thread each in the scan block) and more (a
+    kernel of their own).  The weights span every magnitude from 1 to
+    2^32 - 1, so the totals cover 1 to about 2^51, W = 1 (v = 2^64 - 1) among
+    them."""
+    note(f"parameters D={D} tile={tile}")
+    rng = np.random.default_rng(90 + D)
+    sizes = rng.integers(1, 3000, D) if D > 1 else [1 << 20]
+    ws = []
+    for k, sz in enumerate(sizes):
+        bits = int(rng.integers(1, 33)) if D > 1 else 32
+        ws.append(rng.integers(0, 2 ** bits, int(sz), dtype=np.uint64).astype(np.uint32))
+        if ws[-1].sum() == 0:
+            ws[-1][0] = 1
+    specials = [[1], [3], [2 ** 32 - 1], [1, 0, 0], [2 ** 31, 2 ** 31], [2 ** 32 - 1] * 2999]
+    for k, sp in enumerate(specials if D > 1 else []):
+        ws[k] = np.array(sp, np.uint32)
+    w = np.concatenate(ws)
+    eo = offsets([a.size for a in ws])
+    co = offsets([max(1, a.size // 4) for a in ws])
+    if D == 1:
+        f = rtf.build(to_dev(w), int(co[-1]), tile=tile)
+    else:
+        f = rtf.build_batched(to_dev(w), to_dev(eo), to_dev(co), tile=tile)
+    f.check()
+    got = dist_records(f)
+    want = expected_params(w, eo, co)
+    for d in range(D):
+        g = [int(x) for x in got[d, :7]] + [int(got[d, 7]) & 0xFFFFFFFF]
+        assert g == want[d], f"distribution {d}: {g} != {want[d]}"
+
+
 def test_batched_staged_cells(rtf, orc):
     """Batches with several samples per cell run the kernel that stages a
     distribution's cells in LDS: distributions of at most 1024 cells staged,
