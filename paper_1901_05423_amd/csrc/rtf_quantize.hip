@@ -8,7 +8,7 @@
 // Kernels: k_qinit clears the per-distribution maxima (kept in the low word of
 // scale[d] while the call runs), k_qmax takes the maxima with integer atomics
 // on the float bits (order-preserving for non-negative floats), k_qapply
-// writes q, k_qfinal writes the scales.
+// writes q, k_qfinal writes the scales (for one distribution k_qapply does).
 #include "rtf_internal.h"
 
 namespace rtf {
@@ -241,9 +241,24 @@ __device__ inline double scale_of(const double *scale, int32_t d) {
     return mx > 0.0f ? 4294967295.0 / (double)mx : 0.0;
 }
 
+// One distribution: scale[0] holds either the maximum's float bits in its low
+// word (high word zero, as k_qinit and k_qmax_single leave it) or the final
+// scale, which block 0 of k_qapply writes while other blocks may still read.
+// The two are told apart by the high word: a scale of a positive maximum is
+// at least (2^32 - 1) / FLT_MAX, about 1.3e-29, so its exponent bits are not
+// zero, and a scale of 0 decodes as a maximum of 0.  Both forms give the same
+// bits of s.
+__device__ inline double scale_single(const double *scale) {
+    const uint64_t word = __hip_atomic_load(reinterpret_cast<const uint64_t *>(scale),
+                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (word >> 32) return __longlong_as_double((long long)word);
+    const float mx = __uint_as_float((uint32_t)word);
+    return mx > 0.0f ? 4294967295.0 / (double)mx : 0.0;
+}
+
 __global__ __launch_bounds__(QT) void k_qapply(const float *__restrict__ v,
                                                const int64_t *__restrict__ off, int32_t D,
-                                               int64_t n, const double *scale,
+                                               int64_t n, double *scale,
                                                uint32_t *__restrict__ out) {
     const int64_t b0 = (int64_t)blockIdx.x * QT * QI;
     const int64_t b1 = b0 + (int64_t)QT * QI < n ? b0 + (int64_t)QT * QI : n;
@@ -255,7 +270,10 @@ __global__ __launch_bounds__(QT) void k_qapply(const float *__restrict__ v,
     }
     int32_t d = off ? block_find_segment(off, D, b0) : 0;
     int64_t dend = off ? off[d + 1] : n;
-    double s = scale_of(scale, d);
+    double s = off ? scale_of(scale, d) : scale_single(scale);
+    if (!off && blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(reinterpret_cast<uint64_t *>(scale), (uint64_t)__double_as_longlong(s),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
     for (int k = 0; k < QI; ++k) {
         const int64_t i = b0 + threadIdx.x + (int64_t)QT * k;
@@ -304,7 +322,8 @@ hipError_t launch_quantize(const float *v, const int64_t *elem_off, int32_t D, i
     }
     hipLaunchKernelGGL(k_qapply, dim3((unsigned)nb), dim3(QT), 0, st, v, elem_off, D, n_total,
                        scale, out);
-    hipLaunchKernelGGL(k_qfinal, dim3(db), dim3(256), 0, st, scale, D);
+    // one distribution's scale is written by k_qapply itself
+    if (elem_off) hipLaunchKernelGGL(k_qfinal, dim3(db), dim3(256), 0, st, scale, D);
     return hipGetLastError();
 }
 

@@ -182,6 +182,37 @@ def test_quantize_negative_zero(rtf, orc, batched):
     assert np.array_equal(q.cpu().numpy(), q_ref)
 
 
+@pytest.mark.parametrize("n", [1, 4096, 4097, (1 << 20) + 3])
+def test_quantize_single_scale_extremes(rtf, orc, n):
+    """One distribution's scale, which the apply pass writes while its other
+    blocks still read the maximum: bit for bit against the oracle for the
+    largest float maximum (the smallest scale, about 1.3e-29), a subnormal
+    maximum, an ordinary one and all-zero weights (scale 0), each quantised
+    twice into the same buffers (the second call starts from the first's
+    scale)."""
+    import torch
+    note(f"quantise one distribution n={n}")
+    rng = np.random.default_rng(n)
+    base = rng.random(n).astype(np.float32)
+    cases = {
+        "flt_max": base * np.float32(3.4028235e38),
+        "subnormal": (base * np.float32(1e-40)).astype(np.float32),
+        "ordinary": base,
+        "zero": np.zeros(n, np.float32),
+    }
+    cases["flt_max"][n // 2] = np.float32(3.4028235e38)
+    q = torch.empty(n, dtype=torch.uint32, device="cuda:0")
+    s = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    for name, v in cases.items():
+        q_ref, s_ref = orc.quantize(v)
+        vd = to_dev(v)
+        for _ in range(2):
+            rtf.quantize(vd, out=(q, s))
+            torch.cuda.synchronize()
+            assert s.cpu().numpy()[0] == s_ref[0], name
+            assert np.array_equal(q.cpu().numpy(), q_ref), name
+
+
 def test_deterministic_rebuild(rtf, orc):
     note("determinism n=300000")
     rng = np.random.default_rng(11)
